@@ -1,0 +1,181 @@
+"""Benchmark of the SFHK hot path on one MI355X.
+
+One step = the whole path over one batch: sample the ensemble, propagate
+every live trajectory (RK4 + monodromy + action + HK prefactor +
+recombination + dipole sum), normalise the dipole and take its harmonic
+spectrum.  Workload: N2 (Eq. 7, Table I, eps^2 = 0.5) at fixed alignment 0
+and 90 degrees, 1200 nm / 1.5e14 W/cm^2 / 4-cycle sin^2, dt = 0.05,
+1,048,576 trajectories per angle, FP64.
+
+Prints one JSON line (metric, value, roofline, cpu_baseline, ...).
+"""
+import argparse
+import ctypes as C
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads  # noqa: E402
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X: 256 CU x 4 SIMD x 16 FP64 FMA/clk x 2 x 2.4 GHz
+
+
+def flops_per_step(prob):
+    """Algorithmic FP64 flops of one trajectory-step (FMA = 2), excluding the
+    transcendental calls (sqrt, 1/x, exp, sincos), counted from the formulas:
+    4 potential/gradient/Hessian evaluations, the RK4 stage algebra of
+    (q, p, S), the RK4 of the six monodromy columns, the HK prefactor, the
+    recombination sum over GTO primitives and the amplitude."""
+    screened = any(c["dZ"] != 0.0 for c in prob["target"]["centers"])
+    pot_centre = 60 if screened else 50
+    rhs = 2 * pot_centre + 9
+    qps = 4 * rhs + 92
+    mono = 6 * (4 * 18 + 3 * 24 + 18)
+    pref = 121
+    ns = sum(1 for g in prob["target"]["gto"] if g[1] == 0)
+    npp = len(prob["target"]["gto"]) - ns
+    recomb = 46 + 20 * ns + 32 * npp
+    amp = 16
+    return qps + mono + pref + recomb + amp
+
+
+def cpu_baseline(probs, seeds, budget_s=12.0):
+    import oracle
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    n = 256
+    steps = 0
+    el = 0.0
+    while True:
+        t = time.perf_counter()
+        steps = 0
+        for p, s in zip(probs, seeds):
+            _, ls, _ = oracle.run(p, s, 0, n, cores)
+            steps += ls
+        el = time.perf_counter() - t
+        if el > budget_s / 4 or n >= 65536:
+            break
+        n = min(65536, int(n * max(2.0, budget_s / max(el, 1e-3) / 1.5)))
+    return {"value": steps / el, "unit": "trajectory-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"trajectories 0..{n - 1} of each of the {len(probs)} problems "
+                      f"({steps} live trajectory-steps, {el:.2f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n-traj", type=int, default=1 << 20, help="trajectories per angle")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the path shards by trajectory index with one "
+              "dipole reduction per problem, but only the single-GPU path is built; "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2608_13686_amd as sf
+
+    torch.cuda.set_device(0)
+    wl = workloads.workload_n2_fixed(args.n_traj)
+    probs, n_traj, seeds = wl["problems"], wl["n_traj"], wl["seeds"]
+    stream = torch.cuda.current_stream()
+
+    # buffers resident in HBM before timing
+    total = sum(n_traj)
+    ens = sf.Ensemble(total, len(probs))
+    ens, ws = sf.sample_initial(probs, n_traj, seeds, ens=ens)
+    offs, lens = sf.accum_layout(probs)
+    acc = torch.zeros(sum(lens), dtype=torch.float64, device="cuda")
+    v = torch.empty_like(acc)
+    grids = []
+    for p in probs:
+        N, t0, tau = sf.problem_steps(p)
+        grids.append((t0, 0.5 * tau, sf.harmonic_grid(p, 100.0).cuda()))
+    torch.cuda.synchronize()
+    # live trajectory-steps of this ensemble (unit of work): sum over live of N - k0
+    live_steps = 0
+    for P, (p, o) in enumerate(zip(probs, np.cumsum([0] + n_traj[:-1]))):
+        N = sf.problem_steps(p)[0]
+        k0 = ens.k0[o:o + n_traj[P]]
+        w = ens.w[o:o + n_traj[P]]
+        live_steps += int(((N - k0.to(torch.int64)) * (w > 0)).sum().item())
+    flop_step = [flops_per_step(p) for p in probs]
+    algo_flops = 0.0
+    for P, (p, o) in enumerate(zip(probs, np.cumsum([0] + n_traj[:-1]))):
+        N = sf.problem_steps(p)[0]
+        k0 = ens.k0[o:o + n_traj[P]]
+        w = ens.w[o:o + n_traj[P]]
+        algo_flops += flop_step[P] * float(((N - k0.to(torch.int64)) * (w > 0)).sum().item())
+
+    prop_ms = []
+
+    def step(timed):
+        sf.sample_initial(probs, n_traj, seeds, ens=ens, workspace=ws)
+        acc.zero_()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sf.propagate(probs, ens, accum=acc, workspace=ws)
+        e1.record(stream)
+        sf.dipole(probs, acc, n_traj, v_out=v)
+        for (t0, tauh, om), o, l in zip(grids, offs, lens):
+            sf.spectrum(v[o:o + l], t0, probs[0]["dt"], tauh, om)
+        if timed:
+            prop_ms.append((e0, e1))
+
+    for _ in range(args.warmup):
+        step(False)
+        print(f"warmup step done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    kern_s = np.mean([a.elapsed_time(b) for a, b in prop_ms]) / 1e3
+    print(f"timed {args.steps} steps in {el:.3f} s; propagate {kern_s * 1e3:.1f} ms/launch",
+          file=sys.stderr, flush=True)
+
+    achieved = algo_flops / kern_s / 1e12
+    out = {
+        "metric": "HK trajectory-steps/s (FP64)",
+        "value": live_steps * args.steps / el,
+        "unit": "trajectory-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "problems": "N2 eq7 TableI eps2=0.5, theta 0 and 90 deg",
+                   "laser": "1200nm 1.5e14Wcm2 4cyc sin2 cep0", "dt": 0.05,
+                   "trajectories_per_problem": n_traj[0], "live_trajectory_steps": live_steps,
+                   "precision": "fp64"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": None,
+                     "kernel": "propagate_f64_kernel", "kernel_ms": kern_s * 1e3,
+                     "flops_per_traj_step": flop_step},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(probs, seeds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * sfhk.h -- C ABI of the MI355X strong-field Herman-Kluk (SFHK) hot path.
+ *
+ * The library computes the SFHK estimate of the molecular dipole velocity
+ * and its high-harmonic spectrum (arXiv 2608.13686, Sec. II.A-B):
+ *   1. sample trajectories at the tunnel exit     -> sfhk_sample_initial
+ *   2. propagate them with their monodromy, action,
+ *      HK prefactor and recombination amplitude,
+ *      summing Re a_jk over trajectories          -> sfhk_propagate
+ *   3. normalise the sum into v_z(t_k)             -> sfhk_dipole
+ *   4. Hanning-windowed Fourier transform          -> sfhk_spectrum
+ *
+ * Conventions
+ *  - Atomic units, except the laser (nm, W/cm^2, optical cycles, rad).
+ *  - Every pointer documented as "device" is a HIP device pointer owned by
+ *    the caller; the library never allocates or frees device memory.
+ *    "host" pointers are read during the call only.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  All device work is
+ *    enqueued asynchronously on it; outputs are valid once it completes.
+ *  - Arguments are validated before anything is enqueued: a bad argument
+ *    returns SFHK_E_INVALID and enqueues nothing.  A HIP launch error returns
+ *    SFHK_E_DEVICE.  sfhk_last_error() describes the last failure of the
+ *    calling thread.  No C++ exception crosses this interface.
+ *  - Trajectory j of problem P depends only on (seeds[P], first_index[P] + j):
+ *    splitting an ensemble over calls draws the same trajectories.
+ */
+#ifndef SFHK_H
+#define SFHK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SFHK_ABI_VERSION 1
+#define SFHK_MAX_GTO 64
+#define SFHK_MAX_PROBLEMS 65535
+
+typedef enum {
+  SFHK_OK = 0,
+  SFHK_E_INVALID = 1,     /* bad argument; nothing was enqueued            */
+  SFHK_E_NOMEM = 2,       /* workspace or buffer too small                 */
+  SFHK_E_DEVICE = 3,      /* HIP reported an error                          */
+  SFHK_E_BUSY = 4,        /* resource in use                                */
+  SFHK_E_UNSUPPORTED = 5  /* valid request this build does not implement    */
+} sfhk_status;
+
+typedef enum { SFHK_FP64 = 0, SFHK_MIXED = 1 } sfhk_precision;
+typedef enum { SFHK_ALIGN_FIXED = 0, SFHK_ALIGN_COS2M = 1 } sfhk_align_kind;
+
+/* One centre of the two-centre model potential (Eq. 7, Table I):
+ * V_i = -[Zinf + dZ exp(-alpha rho)] / rho, rho = sqrt(|r - R_i|^2 + eps2).
+ * eps2 = 0 is Eq. 7 itself; dZ = 0 is a soft-core Coulomb centre. */
+typedef struct {
+  double Zinf, dZ, alpha, eps2;
+} sfhk_center;
+
+/* One GTO primitive of psi_0 (Sec. II.A, GTO expansion):
+ * l = 0: c exp(-a |x - R_c|^2);  l = 1: c n.(x - R_c) exp(-a |x - R_c|^2),
+ * centre 0 at +R/2 n, centre 1 at -R/2 n, n the molecular axis. */
+typedef struct {
+  int32_t center; /* 0 or 1          */
+  int32_t l;      /* 0 (s) or 1 (p_n) */
+  double a;       /* exponent > 0    */
+  double c;       /* coefficient     */
+} sfhk_gto;
+
+typedef struct {
+  double R;               /* internuclear distance                         */
+  double Ip;              /* binding energy of psi_0 (hartree), > 0         */
+  sfhk_center ctr[2];     /* ctr[0] at +R/2 n, ctr[1] at -R/2 n             */
+  int32_t n_gto;          /* 1..SFHK_MAX_GTO                                */
+  int32_t reserved;
+  const sfhk_gto* gto;    /* host array [n_gto]                             */
+} sfhk_target;
+
+/* Linearly z-polarised pulse with a sin^2 envelope (Sec. II.D, III.A), centred
+ * at t = 0: A(t) = -(E0/w) cos^2(pi t/tau) sin(w t + cep), |t| <= tau/2,
+ * E = -dA/dt, w = 45.56335252912/lambda_nm, E0 = sqrt(I/3.50944552e16),
+ * tau = n_cycles 2 pi / w.  intensity 0 switches the laser off. */
+typedef struct {
+  double lambda_nm, intensity_wcm2, n_cycles, cep;
+} sfhk_laser;
+
+/* Alignment (Sec. II.B, Eq. 5-6): FIXED axis n = (sin th cos ph, sin th sin ph,
+ * cos th), or COS2M: cos(beta) with density ~ cos^(2m) beta sin beta and alpha
+ * uniform, one axis per trajectory (m = 0 is isotropic). */
+typedef struct {
+  int32_t kind; /* sfhk_align_kind */
+  int32_t m;
+  double theta, phi;
+} sfhk_align;
+
+typedef struct {
+  sfhk_target tgt;
+  sfhk_laser las;
+  sfhk_align al;
+  double dt;         /* RK4 step (a.u.) > 0                                */
+  double gamma_cs;   /* coherent-state width gamma (Sec. II.A uses 1)       */
+  double w_cut;      /* trajectories with weight below it are not propagated */
+  double sigma_perp; /* std. dev. of each transverse initial momentum       */
+  int32_t n_steps;   /* 0: N = round(tau / dt); time grid t_k = -tau/2 + k dt */
+  int32_t reserved;
+} sfhk_problem;
+
+/* Sampled ensemble: structure of arrays in device memory, `capacity` slots.
+ * Problem P owns slots [off_P, off_P + n_per_prob[P]) with off_P the prefix
+ * sum of n_per_prob.  Filled by sfhk_sample_initial:
+ *   k0    birth step (int32), prob problem index (int32),
+ *   q0 = (qx,qy,qz), p0 = (px,py,pz), weight w (0 = not propagated),
+ *   axis n = (nx,ny,nz);
+ *   order[capacity]: slot ids of the live trajectories sorted by (problem,
+ *       k0), ties by slot id; entries past the live total are unspecified;
+ *   live_start[n_prob], live_count[n_prob]: each problem's run in `order`;
+ *   pack_start[n_prob + 1]: prefix sum of ceil(live_count / 64) (one 64-lane
+ *       pack per wavefront; pack_start[n_prob] is the total). */
+typedef struct {
+  uint64_t capacity;
+  int32_t* k0;
+  int32_t* prob;
+  double *qx, *qy, *qz;
+  double *px, *py, *pz;
+  double* w;
+  double *nx, *ny, *nz;
+  uint32_t* order;
+  uint32_t* live_start;
+  uint32_t* live_count;
+  uint32_t* pack_start;
+} sfhk_ensemble;
+
+/* Per-trajectory final state (optional output of sfhk_propagate): device
+ * array [SFHK_FS_COUNT][capacity] (field-major), indexed by slot. */
+enum {
+  SFHK_FS_Q = 0,      /* q(t_N) [3]                                              */
+  SFHK_FS_P = 3,      /* p(t_N) [3]                                              */
+  SFHK_FS_M = 6,      /* monodromy [36], row-major 6x6, rows (q,p), cols (q0,p0) */
+  SFHK_FS_S = 42,     /* continuum action S                                      */
+  SFHK_FS_CRE = 43,   /* HK prefactor C (real)                                   */
+  SFHK_FS_CIM = 44,   /* HK prefactor C (imaginary)                              */
+  SFHK_FS_FLIPS = 45, /* steps with Re(D_k conj(D_{k-1})) < 0                    */
+  SFHK_FS_COUNT = 46
+};
+
+/* SFHK_ABI_VERSION of the library. */
+int32_t sfhk_abi_version(void);
+
+/* Description of the calling thread's last failure ("" if none). */
+const char* sfhk_last_error(void);
+
+/* Host only.  Number of steps N, first grid time t_0 = -tau/2 and pulse length
+ * tau of a problem (Sec. II.D laser; grid t_k = t_0 + k dt, k = 0..N). */
+sfhk_status sfhk_problem_steps(const sfhk_problem* p, int32_t* n_steps, double* t_first,
+                               double* tau);
+
+/* Host only.  Bytes of device workspace that sfhk_sample_initial and
+ * sfhk_propagate need for these problems and `capacity` slots. */
+size_t sfhk_workspace_bytes(const sfhk_problem* probs, int32_t n_prob, uint64_t capacity);
+
+/* Sample the ensemble (Sec. II.A tunnel exit; Sec. II.B joint alignment):
+ * for problem P, trajectories first_index[P] .. + n_per_prob[P] - 1 drawn
+ * from the counter-based Philox4x32-10 stream keyed by seeds[P]; birth step
+ * uniform, p_perp Gaussian, axis by the alignment rule, first-order tunnel
+ * exit, amplitude weight; then sorts the live ones by (problem, k0) into
+ * 64-lane packs.  probs, n_per_prob, seeds, first_index: host arrays
+ * [n_prob]; sum(n_per_prob) <= ens->capacity; workspace: device,
+ * >= sfhk_workspace_bytes. */
+sfhk_status sfhk_sample_initial(const sfhk_problem* probs, int32_t n_prob,
+                                const uint64_t* n_per_prob, const uint64_t* seeds,
+                                const uint64_t* first_index, const sfhk_ensemble* ens,
+                                void* workspace, size_t workspace_bytes, void* stream);
+
+/* Propagate every live trajectory of `ens` from its birth step to t_N with
+ * classical RK4 (Sec. II.A Hamilton's equations in the Eq. 7 potential plus
+ * the laser), its 6x6 monodromy matrix, the action S, the HK prefactor
+ * C = sqrt(det R) (continued branch) and the coherent-state recombination
+ * amplitude a_k = -w C exp(i[S - Ip(t_k - t0) + p0.q0]) <psi0|k_z|p_k,q_k>
+ * (Sec. II.A, Eq. 4-6), and ADD sum_j Re a_jk into accum.
+ *   accum: device double [sum_P (N_P + 1)], problem P at offset
+ *          sum_{Q<P} (N_Q + 1); the caller zeroes it once, calls may add
+ *          further ensembles into it.
+ *   final_state: NULL or device double [SFHK_FS_COUNT][ens->capacity].
+ *   precision: SFHK_FP64 (everything FP64).
+ * probs/n_prob must be those given to sfhk_sample_initial for `ens`. */
+sfhk_status sfhk_propagate(const sfhk_problem* probs, int32_t n_prob, const sfhk_ensemble* ens,
+                           int32_t precision, double* accum, double* final_state,
+                           void* workspace, size_t workspace_bytes, void* stream);
+
+/* Dipole velocity (Sec. II.A, Eq. 4-6): v_k = (2 / n_sampled[P]) accum_k for
+ * each problem (n_sampled counts dropped trajectories too).
+ * accum, v_out: device double, the accum layout; n_sampled: host [n_prob]. */
+sfhk_status sfhk_dipole(const sfhk_problem* probs, int32_t n_prob, const double* accum,
+                        const uint64_t* n_sampled, double* v_out, void* stream);
+
+/* Hanning-windowed Fourier transform (Eq. 3):
+ * V(w_m) = dt sum_k v_k W_H(t_k) exp(i w_m t_k), t_k = t_first + k dt,
+ * W_H = (1 + cos(pi t / tau_H)) / 2 for |t| <= tau_H, else 0;
+ * yield_m = w_m^2 |V(w_m)|^2 (Sec. II.A).
+ * v: device [n_t]; omega: device [n_omega]; V_re, V_im, yield: device [n_omega]. */
+sfhk_status sfhk_spectrum(const double* v, int32_t n_t, double t_first, double dt, double tau_H,
+                          const double* omega, int32_t n_omega, double* V_re, double* V_im,
+                          double* yield, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,185 @@
+"""Python binding of the MI355X SFHK hot path (``libsfhk.so``).
+
+Argument marshalling only: torch tensors own the device memory, the current
+torch stream is the HIP stream, and every step runs in the library's HIP
+kernels.  The names follow the C ABI in ``include/sfhk.h``.
+"""
+import ctypes as C
+import math
+
+import torch
+
+from . import _abi
+from ._abi import FS_COUNT, FS_CIM, FS_CRE, FS_FLIPS, FS_M, FS_P, FS_Q, FS_S, SfhkError
+
+__all__ = ["problem_steps", "workspace_bytes", "Ensemble", "sample_initial", "propagate",
+           "dipole", "spectrum", "run", "SfhkError", "harmonic_grid", "abi_version"]
+
+PRECISION = {"fp64": _abi.FP64, "mixed": _abi.MIXED}
+
+
+def abi_version():
+    return _abi.lib().sfhk_abi_version()
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def problem_steps(prob):
+    """(N, t_first, tau) of a problem dictionary."""
+    arr = _abi.make_problems([prob])
+    n, t0, tau = C.c_int32(), C.c_double(), C.c_double()
+    _abi.check(_abi.lib().sfhk_problem_steps(arr, C.byref(n), C.byref(t0), C.byref(tau)),
+               "sfhk_problem_steps")
+    return n.value, t0.value, tau.value
+
+
+def workspace_bytes(probs, capacity):
+    arr = _abi.make_problems(probs)
+    nb = _abi.lib().sfhk_workspace_bytes(arr, len(probs), int(capacity))
+    if nb == 0:
+        raise SfhkError(1, "sfhk_workspace_bytes")
+    return nb
+
+
+def accum_layout(probs):
+    """(offsets, lengths) of each problem's segment in accum / v arrays."""
+    offs, lens, o = [], [], 0
+    for p in probs:
+        n = problem_steps(p)[0] + 1
+        offs.append(o)
+        lens.append(n)
+        o += n
+    return offs, lens
+
+
+class Ensemble:
+    """Device structure of arrays of a sampled ensemble (see sfhk_ensemble)."""
+
+    FIELDS_I32 = ("k0", "prob")
+    FIELDS_F64 = ("qx", "qy", "qz", "px", "py", "pz", "w", "nx", "ny", "nz")
+
+    def __init__(self, capacity, n_prob, device="cuda"):
+        cap = max(int(capacity), 1)
+        self.capacity = int(capacity)
+        self.n_prob = int(n_prob)
+        for f in self.FIELDS_I32:
+            setattr(self, f, torch.empty(cap, dtype=torch.int32, device=device))
+        for f in self.FIELDS_F64:
+            setattr(self, f, torch.empty(cap, dtype=torch.float64, device=device))
+        self.order = torch.empty(cap, dtype=torch.int32, device=device)
+        self.live_start = torch.empty(n_prob, dtype=torch.int32, device=device)
+        self.live_count = torch.empty(n_prob, dtype=torch.int32, device=device)
+        self.pack_start = torch.empty(n_prob + 1, dtype=torch.int32, device=device)
+
+    def struct(self):
+        s = _abi.Ensemble()
+        s.capacity = self.capacity
+        for f in self.FIELDS_I32 + self.FIELDS_F64 + ("order", "live_start", "live_count",
+                                                         "pack_start"):
+            setattr(s, f, getattr(self, f).data_ptr())
+        return s
+
+
+def sample_initial(probs, n_per_prob, seeds, first_index=None, ens=None, workspace=None,
+                   stream=None, device="cuda"):
+    """Sample and pack an ensemble; returns (Ensemble, workspace tensor)."""
+    n_prob = len(probs)
+    if first_index is None:
+        first_index = [0] * n_prob
+    total = sum(int(n) for n in n_per_prob)
+    if ens is None:
+        ens = Ensemble(total, n_prob, device)
+    arr = _abi.make_problems(probs)
+    nb = _abi.lib().sfhk_workspace_bytes(arr, n_prob, ens.capacity)
+    if nb == 0:
+        raise SfhkError(1, "sfhk_workspace_bytes")
+    if workspace is None or workspace.numel() < nb:
+        workspace = torch.empty(nb, dtype=torch.uint8, device=device)
+    es = ens.struct()
+    _abi.check(_abi.lib().sfhk_sample_initial(
+        arr, n_prob, _abi.u64_array(n_per_prob), _abi.u64_array(seeds),
+        _abi.u64_array(first_index), C.byref(es), C.c_void_p(workspace.data_ptr()),
+        workspace.numel(), _stream(stream)), "sfhk_sample_initial")
+    return ens, workspace
+
+
+def propagate(probs, ens, precision="fp64", accum=None, final_state=False, workspace=None,
+              stream=None):
+    """Propagate the ensemble and add sum_j Re a_jk into accum (created zeroed
+    if None).  Returns (accum, final_state or None)."""
+    n_prob = len(probs)
+    arr = _abi.make_problems(probs)
+    dev = ens.k0.device
+    if accum is None:
+        n_acc = sum(accum_layout(probs)[1])
+        accum = torch.zeros(n_acc, dtype=torch.float64, device=dev)
+    nb = _abi.lib().sfhk_workspace_bytes(arr, n_prob, ens.capacity)
+    if nb == 0:
+        raise SfhkError(1, "sfhk_workspace_bytes")
+    if workspace is None or workspace.numel() < nb:
+        workspace = torch.empty(nb, dtype=torch.uint8, device=dev)
+    fs = None
+    if final_state:
+        fs = torch.zeros((FS_COUNT, max(ens.capacity, 1)), dtype=torch.float64, device=dev)
+    es = ens.struct()
+    _abi.check(_abi.lib().sfhk_propagate(
+        arr, n_prob, C.byref(es), PRECISION[precision], C.c_void_p(accum.data_ptr()),
+        C.c_void_p(fs.data_ptr() if fs is not None else 0), C.c_void_p(workspace.data_ptr()),
+        workspace.numel(), _stream(stream)), "sfhk_propagate")
+    return accum, fs
+
+
+def dipole(probs, accum, n_sampled, v_out=None, stream=None):
+    """v_k = (2/N_s) accum_k per problem."""
+    arr = _abi.make_problems(probs)
+    if v_out is None:
+        v_out = torch.empty_like(accum)
+    _abi.check(_abi.lib().sfhk_dipole(arr, len(probs), C.c_void_p(accum.data_ptr()),
+                                      _abi.u64_array(n_sampled), C.c_void_p(v_out.data_ptr()),
+                                      _stream(stream)), "sfhk_dipole")
+    return v_out
+
+
+def spectrum(v, t_first, dt, tau_H, omega, stream=None):
+    """(V complex128 tensor, yield) of the Hanning-windowed transform (Eq. 3)."""
+    v = v.contiguous()
+    omega = omega.to(device=v.device, dtype=torch.float64).contiguous()
+    n = omega.numel()
+    Vr = torch.empty(n, dtype=torch.float64, device=v.device)
+    Vi = torch.empty_like(Vr)
+    Y = torch.empty_like(Vr)
+    _abi.check(_abi.lib().sfhk_spectrum(
+        C.c_void_p(v.data_ptr()), v.numel(), float(t_first), float(dt), float(tau_H),
+        C.c_void_p(omega.data_ptr()), n, C.c_void_p(Vr.data_ptr()), C.c_void_p(Vi.data_ptr()),
+        C.c_void_p(Y.data_ptr()), _stream(stream)), "sfhk_spectrum")
+    return torch.complex(Vr, Vi), Y
+
+
+def harmonic_grid(prob, h_max, h_step=0.05):
+    """omega on the harmonic grid h = 0:h_step:h_max of the problem's laser."""
+    omega0 = 45.56335252912 / prob["laser"]["lambda_nm"]
+    n = int(round(h_max / h_step)) + 1
+    return torch.arange(n, dtype=torch.float64) * h_step * omega0
+
+
+def run(probs, n_traj, seeds, precision="fp64", h_max=40.0, device="cuda", stream=None):
+    """Whole path for a list of problems: sample, propagate, dipole and the
+    spectrum of each problem on its harmonic grid.  Returns a dict."""
+    ens, ws = sample_initial(probs, n_traj, seeds, device=device, stream=stream)
+    acc, _ = propagate(probs, ens, precision, workspace=ws, stream=stream)
+    v = dipole(probs, acc, n_traj, stream=stream)
+    offs, lens = accum_layout(probs)
+    out = {"v": [], "V": [], "yield": [], "omega": [], "t_first": [], "ensemble": ens}
+    for p, o, n in zip(probs, offs, lens):
+        N, t0, tau = problem_steps(p)
+        om = harmonic_grid(p, h_max).to(device)
+        V, Y = spectrum(v[o:o + n], t0, p["dt"], 0.5 * tau, om, stream=stream)
+        out["v"].append(v[o:o + n])
+        out["V"].append(V)
+        out["yield"].append(Y)
+        out["omega"].append(om)
+        out["t_first"].append(t0)
+    return out

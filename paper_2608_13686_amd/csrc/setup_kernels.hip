@@ -1,0 +1,314 @@
+// Field table, initial-condition sampling, counting sort into 64-lane packs,
+// dipole normalisation and the windowed Fourier transform.
+#include "sfhk_internal.h"
+
+namespace sfhk {
+namespace {
+
+constexpr int kBlock = 256;
+
+__global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint32_t v, uint64_t n) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------- field
+// E(t) = -dA/dt of A(t) = -(E0/w) cos^2(pi t/tau) sin(w t + cep) for
+// |t| <= tau/2, zero outside (sin^2 pulse of Sec. II.D / III.A, centred at
+// t = 0).  Table entries 2k and 2k+1 hold E(t_k) and E(t_k + dt/2).
+__device__ double field_at(const Desc& d, double t) {
+  if (fabs(t) > 0.5 * d.tau) return 0.0;
+  double env = cos(kPi * t / d.tau);
+  double ph = d.omega * t + d.cep;
+  return d.E0 * env * env * cos(ph) -
+         (d.E0 * kPi / (d.omega * d.tau)) * sin(2.0 * kPi * t / d.tau) * sin(ph);
+}
+
+__global__ void field_kernel(const Desc* __restrict__ descs, double* __restrict__ field) {
+  const Desc& d = descs[blockIdx.y];
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > d.N) return;
+  double tk = d.t_first + (double)k * d.dt;
+  field[d.field_off + 2 * (uint64_t)k] = field_at(d, tk);
+  field[d.field_off + 2 * (uint64_t)k + 1] = field_at(d, tk + 0.5 * d.dt);
+}
+
+// -------------------------------------------------------------- Philox
+// Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11):
+// ten rounds of two 32x32 -> 64-bit products and a word permutation, with
+// the two key words advanced by Weyl increments between rounds.
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+__device__ inline double open01(uint32_t x) { return ((double)x + 0.5) * (1.0 / 4294967296.0); }
+
+__device__ inline int find_problem(const uint64_t* __restrict__ off, int n_prob, uint64_t i) {
+  int lo = 0, hi = n_prob;  // off[lo] <= i < off[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (off[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// One thread per ensemble slot.  Initial conditions at the tunnel exit for
+// the first-order expansion of the SFA saddle-point equation (Eq. 2) about
+// the birth time: p0 = (sigma g1, sigma g2, 0), q0 = -(Ip + p0^2/2)/E(t0) z,
+// weight w = (F0/F)^{(2/kappa-1)/2} exp(-(kappa^3/3)(1/F - 1/F0)), F = |E(t0)|,
+// dropped (w = 0) below w_cut; axis fixed or cos^(2m)-distributed (Eq. 6).
+__global__ void sample_kernel(const Desc* __restrict__ descs, int n_prob,
+                              const uint64_t* __restrict__ slot_off, uint64_t n_slots,
+                              const double* __restrict__ field, EnsPtrs e,
+                              uint32_t* __restrict__ hist) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_slots) return;
+  int P = find_problem(slot_off, n_prob, i);
+  const Desc& d = descs[P];
+  uint64_t j = d.first_index + (i - slot_off[P]);
+  uint32_t klo = (uint32_t)d.seed, khi = (uint32_t)(d.seed >> 32);
+  U4 x = philox4x32_10(U4{(uint32_t)j, (uint32_t)(j >> 32), 0u, 0u}, klo, khi);
+  U4 y = philox4x32_10(U4{(uint32_t)j, (uint32_t)(j >> 32), 0u, 1u}, klo, khi);
+
+  int32_t k0 = (int32_t)(((uint64_t)x.x * (uint64_t)d.N) >> 32);
+  double r = sqrt(-2.0 * log(open01(x.y)));
+  double u2 = open01(x.z);
+  double px = d.sigma * r * cos(2.0 * kPi * u2);
+  double py = d.sigma * r * sin(2.0 * kPi * u2);
+
+  double nx, ny, nz;
+  if (d.align_kind == SFHK_ALIGN_FIXED) {
+    nx = d.nfix[0];
+    ny = d.nfix[1];
+    nz = d.nfix[2];
+  } else {
+    double c = 2.0 * open01(x.w) - 1.0;
+    double cb = (c < 0.0 ? -1.0 : 1.0) * pow(fabs(c), 1.0 / (2.0 * d.align_m + 1.0));
+    double sb = sqrt(1.0 - cb * cb);
+    double al = 2.0 * kPi * open01(y.x);
+    nx = sb * cos(al);
+    ny = sb * sin(al);
+    nz = cb;
+  }
+
+  double E = field[d.field_off + 2 * (uint64_t)k0];
+  double F = fabs(E);
+  double w = 0.0, qz = 0.0;
+  if (F > 0.0) {
+    w = pow(d.E0 / F, d.wpow) * exp(-d.kcube3 * (1.0 / F - d.inv_E0));
+    qz = -(d.Ip + 0.5 * (px * px + py * py)) / E;
+  }
+  if (!(w >= d.w_cut)) w = 0.0;
+
+  e.k0[i] = k0;
+  e.prob[i] = P;
+  e.qx[i] = 0.0;
+  e.qy[i] = 0.0;
+  e.qz[i] = qz;
+  e.px[i] = px;
+  e.py[i] = py;
+  e.pz[i] = 0.0;
+  e.w[i] = w;
+  e.nx[i] = nx;
+  e.ny[i] = ny;
+  e.nz[i] = nz;
+  if (w > 0.0) atomicAdd(&hist[d.acc_off + (uint64_t)k0], 1u);
+}
+
+// ------------------------------------------------------ counting sort
+// Exclusive scan of the bin counts in place (single block); entry n holds the
+// total.  Each thread scans one contiguous chunk.
+__global__ void __launch_bounds__(1024) scan_bins_kernel(uint32_t* __restrict__ h, uint64_t n) {
+  __shared__ uint32_t part[1024];
+  const int t = threadIdx.x;
+  uint64_t chunk = (n + 1023) / 1024;
+  uint64_t b = t * chunk, e = b + chunk < n ? b + chunk : n;
+  uint32_t s = 0;
+  for (uint64_t i = b; i < e; ++i) s += h[i];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint32_t v = t >= off ? part[t - off] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - s;  // exclusive prefix of this chunk
+  for (uint64_t i = b; i < e; ++i) {
+    uint32_t c = h[i];
+    h[i] = run;
+    run += c;
+  }
+  if (t == 1023) h[n] = part[1023];
+}
+
+// Per-problem live runs and pack prefix (pack = 64 consecutive live slots).
+__global__ void problem_runs_kernel(const Desc* __restrict__ descs, int n_prob,
+                                    const uint32_t* __restrict__ start, EnsPtrs e) {
+  if (threadIdx.x != 0) return;
+  uint32_t packs = 0;
+  for (int P = 0; P < n_prob; ++P) {
+    const Desc& d = descs[P];
+    uint32_t s0 = start[d.acc_off], s1 = start[d.acc_off + (uint64_t)d.N + 1];
+    e.live_start[P] = s0;
+    e.live_count[P] = s1 - s0;
+    e.pack_start[P] = packs;
+    packs += (s1 - s0 + kWave - 1) / kWave;
+  }
+  e.pack_start[n_prob] = packs;
+}
+
+__global__ void copy_u32_kernel(const uint32_t* __restrict__ a, uint32_t* __restrict__ b,
+                                uint64_t n) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+__global__ void scatter_kernel(const Desc* __restrict__ descs, int n_prob,
+                               const uint64_t* __restrict__ slot_off, uint64_t n_slots,
+                               uint32_t* __restrict__ cursor, EnsPtrs e) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_slots) return;
+  if (!(e.w[i] > 0.0)) return;
+  const Desc& d = descs[e.prob[i]];
+  uint32_t pos = atomicAdd(&cursor[d.acc_off + (uint64_t)e.k0[i]], 1u);
+  e.order[pos] = (uint32_t)i;
+}
+
+// Within each bin the scatter order is arbitrary; sort every bin's slots
+// ascending so that the pack layout is deterministic.
+__global__ void sort_bins_kernel(const uint32_t* __restrict__ start, uint64_t n_bins,
+                                 uint32_t* __restrict__ order) {
+  uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_bins) return;
+  uint32_t lo = start[b], hi = start[b + 1];
+  for (uint32_t i = lo + 1; i < hi; ++i) {
+    uint32_t v = order[i];
+    uint32_t j = i;
+    while (j > lo && order[j - 1] > v) {
+      order[j] = order[j - 1];
+      --j;
+    }
+    order[j] = v;
+  }
+}
+
+// ------------------------------------------------------------- dipole
+__global__ void scale_kernel(const double* __restrict__ in, double* __restrict__ out, double s,
+                             uint64_t n) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = s * in[i];
+}
+
+// ----------------------------------------------------------- spectrum
+// One block per frequency; each thread sums a strided subset of the time
+// grid, then a fixed-order tree reduction (deterministic).
+__global__ void __launch_bounds__(kBlock) spectrum_kernel(const double* __restrict__ v, int n_t,
+                                                          double t_first, double dt,
+                                                          double tau_H,
+                                                          const double* __restrict__ omega,
+                                                          double* __restrict__ V_re,
+                                                          double* __restrict__ V_im,
+                                                          double* __restrict__ yield) {
+  __shared__ double sr[kBlock], si[kBlock];
+  const int m = blockIdx.x;
+  const double w = omega[m];
+  double ar = 0.0, ai = 0.0;
+  for (int k = threadIdx.x; k < n_t; k += kBlock) {
+    double t = t_first + (double)k * dt;
+    double wh = fabs(t) <= tau_H ? 0.5 * (1.0 + cos(kPi * t / tau_H)) : 0.0;
+    double s, c;
+    sincos(w * t, &s, &c);
+    double x = v[k] * wh;
+    ar += x * c;
+    ai += x * s;
+  }
+  sr[threadIdx.x] = ar;
+  si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      sr[threadIdx.x] += sr[threadIdx.x + off];
+      si[threadIdx.x] += si[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double re = dt * sr[0], im = dt * si[0];
+    V_re[m] = re;
+    V_im[m] = im;
+    yield[m] = w * w * (re * re + im * im);
+  }
+}
+
+inline unsigned blocks_for(uint64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_field(const Desc* descs, int n_prob, double* field, uint64_t n_kmax,
+                        hipStream_t s) {
+  // n_kmax: max_P (N_P + 1)
+  hipLaunchKernelGGL(field_kernel, dim3(blocks_for(n_kmax, kBlock), n_prob), dim3(kBlock), 0, s,
+                     descs, field);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample(const Desc* descs, int n_prob, const uint64_t* slot_off,
+                         uint64_t n_slots, const double* field, EnsPtrs e, uint32_t* hist,
+                         hipStream_t s) {
+  if (n_slots == 0) return hipSuccess;
+  hipLaunchKernelGGL(sample_kernel, dim3(blocks_for(n_slots, kBlock)), dim3(kBlock), 0, s, descs,
+                     n_prob, slot_off, n_slots, field, e, hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort(const Desc* descs, int n_prob, const uint64_t* slot_off, uint64_t n_slots,
+                       uint64_t n_bins, uint32_t* hist, uint32_t* cursor, EnsPtrs e,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(scan_bins_kernel, dim3(1), dim3(1024), 0, s, hist, n_bins);
+  hipLaunchKernelGGL(problem_runs_kernel, dim3(1), dim3(64), 0, s, descs, n_prob, hist, e);
+  hipLaunchKernelGGL(copy_u32_kernel, dim3(blocks_for(n_bins + 1, kBlock)), dim3(kBlock), 0, s,
+                     hist, cursor, n_bins + 1);
+  if (n_slots > 0)
+    hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(n_slots, kBlock)), dim3(kBlock), 0, s,
+                       descs, n_prob, slot_off, n_slots, cursor, e);
+  hipLaunchKernelGGL(sort_bins_kernel, dim3(blocks_for(n_bins, kBlock)), dim3(kBlock), 0, s, hist,
+                     n_bins, e.order);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(const double* in, double* out, double scale, uint64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_kernel, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, in, out,
+                     scale, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_spectrum(const double* v, int n_t, double t_first, double dt, double tau_H,
+                           const double* omega, int n_omega, double* V_re, double* V_im,
+                           double* yield, hipStream_t s) {
+  if (n_omega == 0) return hipSuccess;
+  hipLaunchKernelGGL(spectrum_kernel, dim3(n_omega), dim3(kBlock), 0, s, v, n_t, t_first, dt,
+                     tau_H, omega, V_re, V_im, yield);
+  return hipGetLastError();
+}
+
+}  // namespace sfhk

@@ -1,0 +1,85 @@
+// Internal declarations shared by the HIP translation units of libsfhk.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "sfhk.h"
+
+namespace sfhk {
+
+constexpr int kWave = 64;
+constexpr double kPi = 3.14159265358979323846;
+
+// Per-problem constants, derived once on the host and read by every kernel
+// through wave-uniform (scalar) loads.
+struct Desc {
+  // laser and time grid (Sec. II.D pulse, grid t_k = t_first + k dt)
+  double omega, E0, tau, cep, dt, t_first;
+  int32_t N, align_kind, align_m, n_gto;
+  int32_t screened, pad0;
+  // target (Eq. 7) and coherent state
+  double half_R, Ip, gamma, inv_gamma, inv_gamma2, half_inv_gamma;
+  double Zinf[2], dZ[2], alpha[2], eps2[2];
+  // sampling (first-order tunnel exit and amplitude weight)
+  double sigma, w_cut, kappa, wpow, kcube3, inv_E0;
+  double nfix[3];
+  uint64_t seed, first_index;
+  // offsets into shared buffers
+  uint64_t field_off;  // doubles: E(t_k) at 2k, E(t_k + dt/2) at 2k + 1
+  uint64_t acc_off;    // accum / histogram bin of step 0
+  uint64_t slot_off, n_slots;
+  // GTO primitives: centre sign, l, 1/(4 kappa2), 1/(2 kappa2), normalisation,
+  // 1/(2a), with kappa2 = 1/(4a) + 1/(2 gamma)
+  double g_sgn[SFHK_MAX_GTO], g_inv4k[SFHK_MAX_GTO], g_inv2k[SFHK_MAX_GTO];
+  double g_norm[SFHK_MAX_GTO], g_i2a[SFHK_MAX_GTO];
+  int32_t g_l[SFHK_MAX_GTO];
+};
+
+// Device pointers of the ensemble, passed by value to kernels.
+struct EnsPtrs {
+  int32_t* k0;
+  int32_t* prob;
+  double *qx, *qy, *qz, *px, *py, *pz, *w, *nx, *ny, *nz;
+  uint32_t *order, *live_start, *live_count, *pack_start;
+};
+
+// Device workspace carve-up (all offsets 256-byte aligned).
+struct Workspace {
+  Desc* descs;
+  uint64_t* slot_off;   // [n_prob + 1]
+  double* field;        // [sum 2 (N_P + 1)]
+  uint32_t* hist;       // [n_bins + 1] counting-sort bins (then bin starts)
+  uint32_t* cursor;     // [n_bins + 1]
+  size_t bytes;
+};
+
+struct Layout {
+  uint64_t n_bins = 0;        // sum (N_P + 1)
+  uint64_t n_field = 0;       // sum 2 (N_P + 1)
+  uint64_t n_slots = 0;       // sum n_per_prob (sampling) or capacity
+  size_t bytes = 0;
+  size_t off_descs = 0, off_slot = 0, off_field = 0, off_hist = 0, off_cursor = 0;
+};
+
+// launchers (setup_kernels.hip)
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+hipError_t launch_field(const Desc* descs, int n_prob, double* field, uint64_t n_field,
+                        hipStream_t s);
+hipError_t launch_sample(const Desc* descs, int n_prob, const uint64_t* slot_off,
+                         uint64_t n_slots, const double* field, EnsPtrs e, uint32_t* hist,
+                         hipStream_t s);
+hipError_t launch_sort(const Desc* descs, int n_prob, const uint64_t* slot_off, uint64_t n_slots,
+                       uint64_t n_bins, uint32_t* hist, uint32_t* cursor, EnsPtrs e,
+                       hipStream_t s);
+hipError_t launch_scale(const double* in, double* out, double scale, uint64_t n, hipStream_t s);
+hipError_t launch_spectrum(const double* v, int n_t, double t_first, double dt, double tau_H,
+                           const double* omega, int n_omega, double* V_re, double* V_im,
+                           double* yield, hipStream_t s);
+// propagate_f64.hip
+hipError_t launch_propagate_f64(const Desc* descs, int n_prob, const double* field, EnsPtrs e,
+                                uint32_t max_packs, double* accum, double* final_state,
+                                uint64_t capacity, hipStream_t s);
+
+}  // namespace sfhk

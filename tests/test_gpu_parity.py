@@ -1,0 +1,287 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances: relative L2 error of the dipole <= 1e-10 (FP64); integer and
+index outputs bit-exact; per-trajectory final states within a bound that
+grows with the monodromy norm (rounding differences of two correct FP64
+implementations are amplified by |M| along chaotic trajectories).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+REL_L2 = 1e-10
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def sf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2608_13686_amd as sf
+    return sf
+
+
+def rel_l2(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu_sample(sf, probs, n, seeds, first=None):
+    ens, ws = sf.sample_initial(probs, n, seeds, first_index=first)
+    import torch
+    torch.cuda.synchronize()
+    return ens, ws
+
+
+def ens_host(ens):
+    return {f: getattr(ens, f).cpu().numpy() for f in ens.FIELDS_I32 + ens.FIELDS_F64 +
+            ("order", "live_start", "live_count", "pack_start")}
+
+
+# ------------------------------------------------------------- sampling
+@pytest.mark.parametrize("case", ["h2", "n2pair", "cos4", "ragged"])
+def test_sampling_matches_oracle(sf, orc, case):
+    if case == "h2":
+        probs, n, seeds = [workloads.h2_softcore()], [4096], [1001]
+    elif case == "n2pair":
+        probs, n, seeds = [workloads.n2(0.0), workloads.n2(90.0)], [20000, 20000], [1002, 1002]
+    elif case == "cos4":
+        probs = [workloads.n2(align=workloads.cos2m(2)), workloads.h2_softcore(align=workloads.cos2m(2))]
+        n, seeds = [5000, 3000], [77, 78]
+    else:
+        probs = [workloads.h2_softcore(), workloads.n2(30.0), workloads.h2_softcore(60.0)]
+        n, seeds = [1, 0, 1001], [5, 6, 7]
+    first = [123, 0, 99999][:len(probs)]
+    ens, _ = gpu_sample(sf, probs, n, seeds, first)
+    g = ens_host(ens)
+    off = 0
+    for P, (p, nn, sd, f0) in enumerate(zip(probs, n, seeds, first)):
+        o = orc.sample(p, sd, f0, nn)
+        sl = slice(off, off + nn)
+        assert np.array_equal(g["k0"][sl], o["k0"])
+        assert np.all(g["prob"][sl] == P)
+        live_g, live_o = g["w"][sl] > 0, o["w"] > 0
+        # a weight within rounding of the cut may fall either side
+        dis = np.nonzero(live_g != live_o)[0]
+        for i in dis:
+            assert abs(o["w"][i] / p["w_cut"] - 1) < 1e-12
+        both = live_g & live_o
+        assert np.allclose(g["w"][sl][both], o["w"][both], rtol=1e-13, atol=0)
+        for c, f in enumerate(("px", "py", "pz")):
+            assert np.allclose(g[f][sl], o["p0"][:, c], rtol=1e-13, atol=1e-15)
+        for c, f in enumerate(("nx", "ny", "nz")):
+            assert np.allclose(g[f][sl], o["nax"][:, c], rtol=1e-13, atol=1e-15)
+        for c, f in enumerate(("qx", "qy", "qz")):
+            assert np.allclose(g[f][sl][both], o["q0"][both, c], rtol=1e-12, atol=1e-15)
+        off += nn
+    # packs: live slots sorted by (problem, k0, slot), runs and pack prefix
+    live = np.nonzero(g["w"][:off] > 0)[0]
+    want = live[np.lexsort((live, g["k0"][live], g["prob"][live]))]
+    assert np.array_equal(g["order"][:live.size], want)
+    cnt = np.bincount(g["prob"][live], minlength=len(probs))
+    assert np.array_equal(g["live_count"], cnt)
+    assert np.array_equal(g["live_start"], np.concatenate([[0], np.cumsum(cnt)[:-1]]))
+    packs = (cnt + 63) // 64
+    assert np.array_equal(g["pack_start"], np.concatenate([[0], np.cumsum(packs)]))
+
+
+# ---------------------------------------------------------- trajectories
+def check_final_states(sf, orc, probs, n, seeds, picks_per_problem=12, seed=0):
+    import torch
+    ens, ws = gpu_sample(sf, probs, n, seeds)
+    acc, fs = sf.propagate(probs, ens, final_state=True, workspace=ws)
+    torch.cuda.synchronize()
+    fs = fs.cpu().numpy()
+    g = ens_host(ens)
+    rng = np.random.default_rng(seed)
+    off = 0
+    worst = 0.0
+    for p, nn in zip(probs, n):
+        live = off + np.nonzero(g["w"][off:off + nn] > 0)[0]
+        for i in rng.choice(live, size=min(picks_per_problem, live.size), replace=False):
+            _, fo = orc.trajectory(p, int(g["k0"][i]), (g["qx"][i], g["qy"][i], g["qz"][i]),
+                                   (g["px"][i], g["py"][i], g["pz"][i]),
+                                   (g["nx"][i], g["ny"][i], g["nz"][i]), g["w"][i],
+                                   amplitudes=False)
+            fg = fs[:, i]
+            M = fo[6:42].reshape(6, 6)
+            amp = 1.0 + np.linalg.norm(M, 2)
+            N = orc.n_steps(p)
+            steps = N - int(g["k0"][i]) + 1
+            tol = 1e-14 * amp * math.sqrt(steps) * 100
+            err_qp = np.max(np.abs(fg[0:6] - fo[0:6]) / np.maximum(1.0, np.abs(fo[0:6])))
+            err_m = np.max(np.abs(fg[6:42] - fo[6:42])) / amp
+            err_s = abs(fg[42] - fo[42]) / max(1.0, abs(fo[42]))
+            cg, co = fg[43] + 1j * fg[44], fo[43] + 1j * fo[44]
+            err_c = abs(cg - co) / max(1.0, abs(co))
+            worst = max(worst, max(err_qp, err_m, err_s, err_c) / tol)
+            assert err_qp < tol and err_m < tol and err_s < tol and err_c < tol * amp, \
+                (i, err_qp, err_m, err_s, err_c, tol)
+            assert fg[45] == fo[45]
+        off += nn
+    return worst
+
+
+def test_final_states_h2(sf, orc):
+    check_final_states(sf, orc, [workloads.h2_softcore()], [600], [1001])
+
+
+def test_final_states_n2_two_angles_and_cos4(sf, orc):
+    probs = [workloads.n2(0.0), workloads.n2(90.0), workloads.n2(align=workloads.cos2m(2))]
+    check_final_states(sf, orc, probs, [300, 300, 300], [1002, 1002, 5], picks_per_problem=6)
+
+
+# ---------------------------------------------------------------- dipole
+def gpu_dipole(sf, probs, n, seeds, first=None):
+    import torch
+    ens, ws = sf.sample_initial(probs, n, seeds, first_index=first)
+    acc, _ = sf.propagate(probs, ens, workspace=ws)
+    v = sf.dipole(probs, acc, n)
+    torch.cuda.synchronize()
+    offs, lens = sf.accum_layout(probs)
+    return [v[o:o + l].cpu().numpy() for o, l in zip(offs, lens)], acc.cpu().numpy()
+
+
+def test_dipole_h2_full_workload(sf, orc):
+    """The H2 soft-core workload in full: 4096 trajectories, seed 1001."""
+    p = workloads.h2_softcore()
+    (vg,), _ = gpu_dipole(sf, [p], [4096], [1001])
+    vo, _, _ = orc.dipole(p, 1001, 0, 4096, NTHREADS)
+    assert rel_l2(vg, vo) < REL_L2
+
+
+def test_dipole_n2_two_angles(sf, orc):
+    probs = [workloads.n2(0.0), workloads.n2(90.0)]
+    vg, _ = gpu_dipole(sf, probs, [1500, 1500], [1002, 1002])
+    for p, v in zip(probs, vg):
+        vo, _, _ = orc.dipole(p, 1002, 0, 1500, NTHREADS)
+        assert rel_l2(v, vo) < REL_L2
+
+
+def test_dipole_cos4_mixed_molecules(sf, orc):
+    probs = [workloads.h2_softcore(align=workloads.cos2m(2)),
+             workloads.n2(align=workloads.cos2m(2),
+                          laser=dict(workloads.N2_LASER, intensity_wcm2=2.5e14, cep=math.pi / 4))]
+    n = [777, 555]
+    vg, _ = gpu_dipole(sf, probs, n, [11, 12])
+    for p, v, nn, sd in zip(probs, vg, n, [11, 12]):
+        vo, _, _ = orc.dipole(p, sd, 0, nn, NTHREADS)
+        assert rel_l2(v, vo) < REL_L2
+
+
+def test_split_calls_equal_one_call(sf):
+    """Trajectory j depends only on (seed, first_index + j): two halves added
+    into one accumulator equal the whole."""
+    import torch
+    p = [workloads.h2_softcore(20.0)]
+    (v_all,), acc_all = gpu_dipole(sf, p, [3000], [9])
+    ens1, ws = sf.sample_initial(p, [1000], [9], first_index=[0])
+    acc, _ = sf.propagate(p, ens1, workspace=ws)
+    ens2, ws = sf.sample_initial(p, [2000], [9], first_index=[1000])
+    acc, _ = sf.propagate(p, ens2, accum=acc, workspace=ws)
+    torch.cuda.synchronize()
+    assert rel_l2(acc.cpu().numpy(), acc_all) < 1e-13
+
+
+def test_edge_cases(sf, orc):
+    import torch
+    # all trajectories dropped: weak laser, every weight under the cut
+    weak = workloads.with_changes(workloads.h2_softcore(), **{"laser.intensity_wcm2": 1e11})
+    (v,), _ = gpu_dipole(sf, [weak], [500], [1])
+    assert np.all(v == 0)
+    # laser off: every weight is zero
+    (v,), _ = gpu_dipole(sf, [workloads.laser_off(workloads.h2_softcore())], [64], [1])
+    assert np.all(v == 0)
+    # one trajectory; empty problem between two others; ragged sizes
+    probs = [workloads.h2_softcore(), workloads.n2(10.0), workloads.h2_softcore(45.0)]
+    n = [1, 0, 130]
+    vg, _ = gpu_dipole(sf, probs, n, [1001, 3, 4])
+    for p, v, nn, sd in zip(probs, vg, n, [1001, 3, 4]):
+        if nn == 0:
+            assert np.all(v == 0)
+            continue
+        vo, _, _ = orc.dipole(p, sd, 0, nn, NTHREADS)
+        if np.linalg.norm(vo) == 0:
+            assert np.all(v == 0)
+        else:
+            assert rel_l2(v, vo) < REL_L2
+    # a birth at the very last step contributes only its birth amplitude
+    p = workloads.h2_softcore()
+    s = orc.sample(p, 1001, 0, 4096)
+    assert s["k0"].max() <= orc.n_steps(p) - 1
+
+
+# -------------------------------------------------------------- spectrum
+def test_spectrum_matches_oracle(sf, orc):
+    import torch
+    rng = np.random.default_rng(4)
+    p = workloads.h2_softcore()
+    N, t0, tau = sf.problem_steps(p)
+    v = rng.normal(size=N + 1)
+    om = sf.harmonic_grid(p, 40.0)
+    V, Y = sf.spectrum(torch.tensor(v, device="cuda"), t0, p["dt"], tau / 2, om.cuda())
+    torch.cuda.synchronize()
+    Vo, Yo = orc.spectrum(v, t0, p["dt"], tau / 2, om.numpy())
+    assert rel_l2(V.cpu().numpy(), Vo) < 1e-12
+    assert rel_l2(Y.cpu().numpy(), Yo) < 1e-12
+
+
+def test_whole_path_spectrum_h2(sf, orc):
+    """Dipole and harmonic spectrum of the H2 workload (harmonics 0..40)."""
+    p = workloads.h2_softcore()
+    out = sf.run([p], [4096], [1001], h_max=40.0)
+    import torch
+    torch.cuda.synchronize()
+    vo, _, _ = orc.dipole(p, 1001, 0, 4096, NTHREADS)
+    N, t0, tau = sf.problem_steps(p)
+    Vo, Yo = orc.spectrum(vo, t0, p["dt"], tau / 2, out["omega"][0].cpu().numpy())
+    assert rel_l2(out["V"][0].cpu().numpy(), Vo) < REL_L2
+    assert rel_l2(out["yield"][0].cpu().numpy(), Yo) < 2 * REL_L2
+
+
+# ------------------------------------------------- full-size workload
+def test_full_size_n2_sampled_trajectories_and_linearity(sf, orc):
+    """The N2 workload at its full size (2 x 1,048,576) in the benchmark's
+    launch configuration: sampled trajectories against the oracle one by one,
+    and the dipole against the sum of two independently launched halves."""
+    import torch
+    probs = [workloads.n2(0.0), workloads.n2(90.0)]
+    n = [1 << 20, 1 << 20]
+    seeds = [1002, 1002]
+    ens, ws = sf.sample_initial(probs, n, seeds)
+    acc, fs = sf.propagate(probs, ens, final_state=True, workspace=ws)
+    torch.cuda.synchronize()
+    g = ens_host(ens)
+    fs = fs.cpu().numpy()
+    rng = np.random.default_rng(1)
+    off = 0
+    for p, nn in zip(probs, n):
+        live = off + np.nonzero(g["w"][off:off + nn] > 0)[0]
+        assert 0.3 < live.size / nn < 0.7
+        for i in rng.choice(live, size=6, replace=False):
+            _, fo = orc.trajectory(p, int(g["k0"][i]), (g["qx"][i], g["qy"][i], g["qz"][i]),
+                                   (g["px"][i], g["py"][i], g["pz"][i]),
+                                   (g["nx"][i], g["ny"][i], g["nz"][i]), g["w"][i],
+                                   amplitudes=False)
+            amp = 1.0 + np.linalg.norm(fo[6:42].reshape(6, 6), 2)
+            tol = 1e-10 * amp
+            assert np.max(np.abs(fs[0:6, i] - fo[0:6]) / np.maximum(1, np.abs(fo[0:6]))) < tol
+            assert abs(fs[42, i] - fo[42]) / max(1, abs(fo[42])) < tol
+        off += nn
+    acc_full = acc.cpu().numpy()
+    del ens, ws, fs
+    half = [1 << 19, 1 << 19]
+    acc2 = torch.zeros_like(acc)
+    for first in (0, 1 << 19):
+        e, w = sf.sample_initial(probs, half, seeds, first_index=[first, first])
+        sf.propagate(probs, e, accum=acc2, workspace=w)
+    torch.cuda.synchronize()
+    assert rel_l2(acc2.cpu().numpy(), acc_full) < 1e-11
