@@ -31,7 +31,21 @@ def sf():
 def rel_l2(a, b):
     a = np.asarray(a)
     b = np.asarray(b)
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    r = float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    print(f"relative L2 error {r:.3e}")
+    return r
+
+
+def rel_err(a, b, floor=0.0):
+    """max |a - b| / max(|b|, floor), printed for the record."""
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    if a.size == 0:
+        return 0.0
+    e = np.abs(a - b) / np.maximum(np.abs(b), floor if floor > 0 else 1e-300)
+    e[(a == b)] = 0.0
+    i = int(np.argmax(e))
+    print(f"max rel err {e[i]:.3e} at {i}: {a[i]!r} vs {b[i]!r}")
+    return float(e[i])
 
 
 def gpu_sample(sf, probs, n, seeds, first=None):
@@ -74,13 +88,15 @@ def test_sampling_matches_oracle(sf, orc, case):
         for i in dis:
             assert abs(o["w"][i] / p["w_cut"] - 1) < 1e-12
         both = live_g & live_o
-        assert np.allclose(g["w"][sl][both], o["w"][both], rtol=1e-13, atol=0)
+        # transcendental results of the device library and of libm may differ
+        # by a few ulps; the weight's exponent (kappa^3/3)/F amplifies them
+        assert rel_err(g["w"][sl][both], o["w"][both]) < 1e-12
         for c, f in enumerate(("px", "py", "pz")):
-            assert np.allclose(g[f][sl], o["p0"][:, c], rtol=1e-13, atol=1e-15)
-        for c, f in enumerate(("nx", "ny", "nz")):
-            assert np.allclose(g[f][sl], o["nax"][:, c], rtol=1e-13, atol=1e-15)
+            assert rel_err(g[f][sl], o["p0"][:, c], 1e-15) < 1e-13, f
+        for c, f in enumerate(("nx", "ny", "nz")):  # unit vector: absolute error
+            assert rel_err(g[f][sl], o["nax"][:, c], 1.0) < 1e-14, f
         for c, f in enumerate(("qx", "qy", "qz")):
-            assert np.allclose(g[f][sl][both], o["q0"][both, c], rtol=1e-12, atol=1e-15)
+            assert rel_err(g[f][sl][both], o["q0"][both, c], 1e-15) < 1e-12, f
         off += nn
     # packs: live slots sorted by (problem, k0, slot), runs and pack prefix
     live = np.nonzero(g["w"][:off] > 0)[0]
