@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-traj", type=int, default=1 << 20, help="trajectories per angle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path shards by trajectory index with one "
@@ -88,6 +90,13 @@ def main():
     import paper_2608_13686_amd as sf
 
     torch.cuda.set_device(0)
+    if args.copy_mib > 0:
+        a = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     wl = workloads.workload_n2_fixed(args.n_traj)
     probs, n_traj, seeds = wl["problems"], wl["n_traj"], wl["seeds"]
     stream = torch.cuda.current_stream()
