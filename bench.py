@@ -27,23 +27,43 @@ import workloads  # noqa: E402
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X: 256 CU x 4 SIMD x 16 FP64 FMA/clk x 2 x 2.4 GHz
 
 
-def flops_per_step(prob):
+def flops_per_step(prob, with_recombination=False):
     """Algorithmic FP64 flops of one trajectory-step (FMA = 2), excluding the
     transcendental calls (sqrt, 1/x, exp, sincos), counted from the formulas:
     4 potential/gradient/Hessian evaluations, the RK4 stage algebra of
-    (q, p, S), the RK4 of the six monodromy columns, the HK prefactor, the
-    recombination sum over GTO primitives and the amplitude."""
+    (q, p, S), the RK4 of the six monodromy columns, the HK prefactor and the
+    amplitude.  The recombination sum over GTO primitives is added only with
+    with_recombination=True: the kernel skips primitives whose term is below
+    1e-30, so the roofline numerator leaves it out (a lower bound)."""
     screened = any(c["dZ"] != 0.0 for c in prob["target"]["centers"])
     pot_centre = 60 if screened else 50
     rhs = 2 * pot_centre + 9
     qps = 4 * rhs + 92
     mono = 6 * (4 * 18 + 3 * 24 + 18)
     pref = 121
-    ns = sum(1 for g in prob["target"]["gto"] if g[1] == 0)
-    npp = len(prob["target"]["gto"]) - ns
-    recomb = 46 + 20 * ns + 32 * npp
     amp = 16
-    return qps + mono + pref + recomb + amp
+    total = qps + mono + pref + amp
+    if with_recombination:
+        ns = sum(1 for g in prob["target"]["gto"] if g[1] == 0)
+        npp = len(prob["target"]["gto"]) - ns
+        total += 46 + 20 * ns + 32 * npp
+    return total
+
+
+def measured_traffic(kernel_file, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the kernel source as it is now; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel_file}__{workload}.traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    csrc = os.path.join(ROOT, "paper_2608_13686_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, f), "rb").read()
+                   for f in ("propagate_f64.hip", "sfhk_internal.h"))
+    if hashlib.sha256(src).hexdigest() != rec["kernel_sha256"]:
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
 
 
 def cpu_baseline(probs, seeds, budget_s=12.0):
@@ -177,9 +197,11 @@ def main():
                    "precision": "fp64"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": None,
+                     "traffic": measured_traffic("propagate_f64_kernel",
+                                                 "n2_fixed_0_90_2x1048576") if args.n_traj == 1 << 20 else None,
                      "kernel": "propagate_f64_kernel", "kernel_ms": kern_s * 1e3,
-                     "flops_per_traj_step": flop_step},
+                     "flops_per_traj_step": flop_step,
+                     "flops_per_traj_step_with_recombination": [flops_per_step(p, True) for p in probs]},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(probs, seeds)
