@@ -141,6 +141,10 @@ Desc make_desc(const sfhk_problem& p) {
     d.dZ[c] = p.tgt.ctr[c].dZ;
     d.alpha[c] = p.tgt.ctr[c].alpha;
     d.eps2[c] = p.tgt.ctr[c].eps2;
+    d.fZinf[c] = (float)d.Zinf[c];
+    d.fdZ[c] = (float)d.dZ[c];
+    d.falpha[c] = (float)d.alpha[c];
+    d.feps2[c] = (float)d.eps2[c];
   }
   d.sigma = p.sigma_perp;
   d.w_cut = p.w_cut;
@@ -152,6 +156,7 @@ Desc make_desc(const sfhk_problem& p) {
   d.nfix[1] = std::sin(p.al.theta) * std::sin(p.al.phi);
   d.nfix[2] = std::cos(p.al.theta);
   const double g = p.gamma_cs;
+  d.g_inv4k_min = 1e300;
   for (int j = 0; j < p.tgt.n_gto; ++j) {
     const sfhk_gto& G = p.tgt.gto[j];
     const double k2 = 1.0 / (4.0 * G.a) + 1.0 / (2.0 * g);
@@ -162,6 +167,7 @@ Desc make_desc(const sfhk_problem& p) {
     d.g_norm[j] = G.c * std::pow(2.0 * G.a, -1.5) * std::pow(kPi * g, -0.75) *
                   std::pow(kPi / k2, 1.5);
     d.g_i2a[j] = 1.0 / (2.0 * G.a);
+    d.g_inv4k_min = std::min(d.g_inv4k_min, d.g_inv4k[j]);
   }
   return d;
 }
@@ -200,6 +206,12 @@ Layout build_layout(const sfhk_problem* probs, int32_t n_prob, uint64_t n_slots,
   off = align256(off + sizeof(uint32_t) * (size_t)(L.n_bins + 1));
   L.off_cursor = off;
   off = align256(off + sizeof(uint32_t) * (size_t)(L.n_bins + 1));
+  L.off_redo = off;
+  off = align256(off + sizeof(int32_t) * (size_t)n_slots);
+  L.off_order2 = off;
+  off = align256(off + sizeof(uint32_t) * (size_t)n_slots);
+  L.off_runs2 = off;
+  off = align256(off + sizeof(uint32_t) * (3 * (size_t)n_prob + 1));
   L.bytes = off;
   if (max_steps) *max_steps = mx;
   return L;
@@ -213,6 +225,9 @@ Workspace carve(void* base, const Layout& L) {
   w.field = reinterpret_cast<double*>(b + L.off_field);
   w.hist = reinterpret_cast<uint32_t*>(b + L.off_hist);
   w.cursor = reinterpret_cast<uint32_t*>(b + L.off_cursor);
+  w.redo = reinterpret_cast<int32_t*>(b + L.off_redo);
+  w.order2 = reinterpret_cast<uint32_t*>(b + L.off_order2);
+  w.runs2 = reinterpret_cast<uint32_t*>(b + L.off_runs2);
   w.bytes = L.bytes;
   return w;
 }
@@ -335,8 +350,9 @@ sfhk_status sfhk_sample_initial(const sfhk_problem* probs, int32_t n_prob,
   hipError_t e = launch_fill_u32(ws.hist, 0u, L.n_bins + 1, s);
   if (e == hipSuccess) e = launch_sample(ws.descs, n_prob, ws.slot_off, n_slots, ws.field, ep,
                                          ws.hist, s);
-  if (e == hipSuccess) e = launch_sort(ws.descs, n_prob, ws.slot_off, n_slots, L.n_bins, ws.hist,
-                                       ws.cursor, ep, s);
+  PackOut po{ep.order, ep.live_start, ep.live_count, ep.pack_start};
+  if (e == hipSuccess)
+    e = launch_sort(ws.descs, n_prob, n_slots, L.n_bins, ws.hist, ws.cursor, ep, nullptr, po, s);
   if (e != hipSuccess) return hip_fail(e, "sample_initial");
   return ok();
 }
@@ -349,8 +365,6 @@ sfhk_status sfhk_propagate(const sfhk_problem* probs, int32_t n_prob, const sfhk
   if ((st = check_ensemble(ens)) != SFHK_OK) return st;
   if (precision != SFHK_FP64 && precision != SFHK_MIXED)
     return fail(SFHK_E_INVALID, "unknown precision %d", precision);
-  if (precision != SFHK_FP64)
-    return fail(SFHK_E_UNSUPPORTED, "precision %d is not available in this build", precision);
   if (!accum) return fail(SFHK_E_INVALID, "accum is null");
   std::vector<Desc> descs;
   int64_t max_steps = 0;
@@ -365,8 +379,35 @@ sfhk_status sfhk_propagate(const sfhk_problem* probs, int32_t n_prob, const sfhk
   // one wavefront per 64-lane pack; packs never straddle problems
   const uint64_t max_packs = (ens->capacity + kWave - 1) / kWave + (uint64_t)n_prob;
   if (max_packs > 0x7fffffffull) return fail(SFHK_E_UNSUPPORTED, "ensemble too large");
-  hipError_t e = launch_propagate_f64(ws.descs, n_prob, ws.field, ens_ptrs(ens),
-                                      (uint32_t)max_packs, accum, final_state, ens->capacity, s);
+  EnsPtrs ep = ens_ptrs(ens);
+  hipError_t e;
+  if (precision == SFHK_FP64) {
+    e = launch_propagate_f64(ws.descs, n_prob, ws.field, ep, nullptr, (uint32_t)max_packs, accum,
+                             final_state, ens->capacity, s);
+  } else {
+    // FP32 stepping for every trajectory; those whose monodromy matrix grows
+    // past the FP32 bound are handed over, at that step, to an FP64 re-run
+    // from their birth (sorted into packs of their own).
+    e = launch_fill_i32(ws.redo, -1, ens->capacity, s);
+    if (e == hipSuccess)
+      e = launch_propagate_mixed(ws.descs, n_prob, ws.field, ep, ws.redo, (uint32_t)max_packs,
+                                 accum, final_state, ens->capacity, s);
+    if (e == hipSuccess) e = launch_fill_u32(ws.hist, 0u, L.n_bins + 1, s);
+    if (e == hipSuccess) e = launch_count(ws.descs, ens->capacity, ep, ws.redo, ws.hist, s);
+    PackOut po{ws.order2, ws.runs2, ws.runs2 + n_prob, ws.runs2 + 2 * n_prob};
+    if (e == hipSuccess)
+      e = launch_sort(ws.descs, n_prob, ens->capacity, L.n_bins, ws.hist, ws.cursor, ep, ws.redo,
+                      po, s);
+    if (e == hipSuccess) {
+      EnsPtrs e2 = ep;
+      e2.order = po.order;
+      e2.live_start = po.live_start;
+      e2.live_count = po.live_count;
+      e2.pack_start = po.pack_start;
+      e = launch_propagate_f64(ws.descs, n_prob, ws.field, e2, ws.redo, (uint32_t)max_packs,
+                               accum, final_state, ens->capacity, s);
+    }
+  }
   if (e != hipSuccess) return hip_fail(e, "propagate");
   return ok();
 }

@@ -1,0 +1,228 @@
+// Mixed-precision trajectory kernel: positions, momenta, the potential, its
+// Hessian, the 6x6 monodromy matrix and det R are computed in FP32; the
+// action S is accumulated in FP64 (from FP32 stage Lagrangians), and the
+// square root of det R with its branch, the recombination element, the
+// amplitude and the dipole sum are FP64.
+// One trajectory per lane, one 64-lane pack per wavefront; the whole state
+// fits in VGPRs (no LDS).
+#include "device_common.h"
+
+namespace sfhk {
+namespace {
+
+__global__ void __launch_bounds__(kWave)
+propagate_mixed_kernel(const Desc* __restrict__ descs, int n_prob,
+                       const double* __restrict__ field, EnsPtrs e, int32_t* __restrict__ redo,
+                       double* __restrict__ accum, double* __restrict__ final_state,
+                       uint64_t capacity) {
+  const int lane = threadIdx.x;
+  Pack pk;
+  if (!find_pack(e, n_prob, blockIdx.x, lane, pk)) return;
+  const Desc& d = descs[pk.prob];
+  const int N = d.N;
+  const bool valid = pk.valid;
+  const uint32_t slot = pk.slot;
+
+  // initial conditions (FP64 as sampled; FP32 copies for the stepping)
+  const int k0 = valid ? e.k0[slot] : N + 1;
+  const double q0d[3] = {e.qx[slot], e.qy[slot], e.qz[slot]};
+  const double p0d[3] = {e.px[slot], e.py[slot], e.pz[slot]};
+  const double n[3] = {e.nx[slot], e.ny[slot], e.nz[slot]};
+  const double w = e.w[slot];
+  const double t0 = d.t_first + (double)k0 * d.dt;
+  const double p0q0 = p0d[0] * q0d[0] + p0d[1] * q0d[1] + p0d[2] * q0d[2];
+  float q[3] = {(float)q0d[0], (float)q0d[1], (float)q0d[2]};
+  float p[3] = {(float)p0d[0], (float)p0d[1], (float)p0d[2]};
+  const float hRn[3] = {(float)(d.half_R * n[0]), (float)(d.half_R * n[1]),
+                        (float)(d.half_R * n[2])};
+  double S = 0.0;
+  float mq[3][6], mp[3][6];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      mq[r][c] = (c == r) ? 1.0f : 0.0f;
+      mp[r][c] = (c == r + 3) ? 1.0f : 0.0f;
+    }
+  double Cre = 1.0, Cim = 0.0, flips = 0.0;
+
+  const double hd = d.dt;
+  const float h = (float)d.dt;
+  const float hh = 0.5f * h, h6 = h / 6.0f;
+  const double* __restrict__ fe = field + d.field_off;
+  double* __restrict__ acc = accum + d.acc_off;
+  const int kmin = __builtin_amdgcn_readfirstlane(k0);
+  double acc_reg = 0.0;
+  int kend = N + 1;  // first step left to the FP64 re-run (N + 1: none)
+
+  for (int k = kmin;; ++k) {
+    const bool live = k >= k0 && k < kend;
+    double re_a = 0.0;
+    if (live) {
+      // HK matrix and its determinant from the FP32 monodromy matrix, in FP32;
+      // the square root, its branch and the amplitude in FP64
+      const float ig = (float)d.inv_gamma, gm = (float)d.gamma;
+      float Rr[3][3], Ri[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          Rr[a][b] = 0.5f * (mq[a][b] + mp[a][3 + b]);
+          Ri[a][b] = 0.5f * (ig * mp[a][b] - gm * mq[a][3 + b]);
+        }
+      float Dr, Di;
+      det3c(Rr, Ri, Dr, Di);
+      sqrt_continued((double)Dr, (double)Di, Cre, Cim, flips);
+      const double pd_[3] = {(double)p[0], (double)p[1], (double)p[2]};
+      const double qd_[3] = {(double)q[0], (double)q[1], (double)q[2]};
+      re_a = amplitude_re(d, n, pd_, qd_, Cre, Cim, S, d.t_first + (double)k * hd, t0, p0q0, w);
+    }
+    deposit(re_a, k, N, lane, acc_reg, acc);
+    if (k >= N) break;
+    if (!live) continue;
+
+    // --- classical RK4 step t_k -> t_{k+1}; (q, p, M) in FP32, S in FP64
+    const float Ek = (float)fe[2 * k], Eh = (float)fe[2 * k + 1], E1 = (float)fe[2 * k + 2];
+    float K1[6], K2[6], K3[6], K4[6];
+    float V, g[3];
+    float sq[3], sp3[3], yq[3], yp[3];
+    float sS;  // weighted sum of the stage Lagrangians p^2/2 - V - q_z E
+
+    potential(d, hRn, q, V, g, K1);
+    {
+      const float kp[3] = {-g[0], -g[1], -g[2] - Ek};
+      sS = 0.5f * (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]) - V - q[2] * Ek;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        sq[a] = p[a];
+        sp3[a] = kp[a];
+        yq[a] = q[a] + hh * p[a];
+        yp[a] = p[a] + hh * kp[a];
+      }
+    }
+    potential(d, hRn, yq, V, g, K2);
+    {
+      const float kp[3] = {-g[0], -g[1], -g[2] - Eh};
+      sS += 2.0f * (0.5f * (yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]) - V - yq[2] * Eh);
+      const float kq[3] = {yp[0], yp[1], yp[2]};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        sq[a] += 2.0f * kq[a];
+        sp3[a] += 2.0f * kp[a];
+        yq[a] = q[a] + hh * kq[a];
+        yp[a] = p[a] + hh * kp[a];
+      }
+    }
+    potential(d, hRn, yq, V, g, K3);
+    {
+      const float kp[3] = {-g[0], -g[1], -g[2] - Eh};
+      sS += 2.0f * (0.5f * (yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]) - V - yq[2] * Eh);
+      const float kq[3] = {yp[0], yp[1], yp[2]};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        sq[a] += 2.0f * kq[a];
+        sp3[a] += 2.0f * kp[a];
+        yq[a] = q[a] + h * kq[a];
+        yp[a] = p[a] + h * kp[a];
+      }
+    }
+    potential(d, hRn, yq, V, g, K4);
+    {
+      const float kp[3] = {-g[0], -g[1], -g[2] - E1};
+      sS += 0.5f * (yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]) - V - yq[2] * E1;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        sq[a] += yp[a];
+        sp3[a] += kp[a];
+        q[a] = q[a] + h6 * sq[a];
+        p[a] = p[a] + h6 * sp3[a];
+      }
+      S = S + (hd / 6.0) * (double)sS;
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const float x0[3] = {mq[0][c], mq[1][c], mq[2][c]};
+      const float v0[3] = {mp[0][c], mp[1][c], mp[2][c]};
+      float a[3], xs[3], vs[3], sx[3], sv[3];
+      symmul(K1, x0, a);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        sx[r] = v0[r];
+        sv[r] = -a[r];
+        xs[r] = x0[r] + hh * v0[r];
+        vs[r] = v0[r] - hh * a[r];
+      }
+      symmul(K2, xs, a);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const float kx = vs[r];
+        sx[r] += 2.0f * kx;
+        sv[r] -= 2.0f * a[r];
+        xs[r] = x0[r] + hh * kx;
+        vs[r] = v0[r] - hh * a[r];
+      }
+      symmul(K3, xs, a);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const float kx = vs[r];
+        sx[r] += 2.0f * kx;
+        sv[r] -= 2.0f * a[r];
+        xs[r] = x0[r] + h * kx;
+        vs[r] = v0[r] - h * a[r];
+      }
+      symmul(K4, xs, a);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        sx[r] += vs[r];
+        sv[r] -= a[r];
+        mq[r][c] = x0[r] + h6 * sx[r];
+        mp[r][c] = v0[r] + h6 * sv[r];
+      }
+    }
+    // FP32 rounding is amplified by the monodromy matrix: past the bound the
+    // trajectory is finished by the FP64 kernel from step k + 1 on
+    float mmax = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) mmax = fmaxf(mmax, fmaxf(fabsf(mq[r][c]), fabsf(mp[r][c])));
+    if (mmax > kMixedFlagNorm) {
+      kend = k + 1;
+      redo[slot] = kend;
+    }
+  }
+
+  if (final_state != nullptr && valid && kend > N) {
+    double* f = final_state + slot;
+    const uint64_t st = capacity;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      f[(SFHK_FS_Q + a) * st] = (double)q[a];
+      f[(SFHK_FS_P + a) * st] = (double)p[a];
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        f[(SFHK_FS_M + 6 * r + c) * st] = (double)mq[r][c];
+        f[(SFHK_FS_M + 6 * (3 + r) + c) * st] = (double)mp[r][c];
+      }
+    f[SFHK_FS_S * st] = S;
+    f[SFHK_FS_CRE * st] = Cre;
+    f[SFHK_FS_CIM * st] = Cim;
+    f[SFHK_FS_FLIPS * st] = flips;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_propagate_mixed(const Desc* descs, int n_prob, const double* field, EnsPtrs e,
+                                  int32_t* redo, uint32_t max_packs, double* accum,
+                                  double* final_state, uint64_t capacity, hipStream_t s) {
+  if (max_packs == 0) return hipSuccess;
+  hipLaunchKernelGGL(propagate_mixed_kernel, dim3(max_packs), dim3(kWave), 0, s, descs, n_prob,
+                     field, e, redo, accum, final_state, capacity);
+  return hipGetLastError();
+}
+
+}  // namespace sfhk

@@ -156,18 +156,34 @@ __global__ void __launch_bounds__(1024) scan_bins_kernel(uint32_t* __restrict__ 
 
 // Per-problem live runs and pack prefix (pack = 64 consecutive live slots).
 __global__ void problem_runs_kernel(const Desc* __restrict__ descs, int n_prob,
-                                    const uint32_t* __restrict__ start, EnsPtrs e) {
+                                    const uint32_t* __restrict__ start, PackOut o) {
   if (threadIdx.x != 0) return;
   uint32_t packs = 0;
   for (int P = 0; P < n_prob; ++P) {
     const Desc& d = descs[P];
     uint32_t s0 = start[d.acc_off], s1 = start[d.acc_off + (uint64_t)d.N + 1];
-    e.live_start[P] = s0;
-    e.live_count[P] = s1 - s0;
-    e.pack_start[P] = packs;
+    o.live_start[P] = s0;
+    o.live_count[P] = s1 - s0;
+    o.pack_start[P] = packs;
     packs += (s1 - s0 + kWave - 1) / kWave;
   }
-  e.pack_start[n_prob] = packs;
+  o.pack_start[n_prob] = packs;
+}
+
+__device__ __forceinline__ bool selected(const EnsPtrs& e, const int32_t* select, uint64_t i) {
+  return select ? select[i] >= 0 : e.w[i] > 0.0;
+}
+
+__global__ void count_kernel(const Desc* __restrict__ descs, uint64_t n_slots, EnsPtrs e,
+                             const int32_t* __restrict__ select, uint32_t* __restrict__ hist) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_slots || !selected(e, select, i)) return;
+  atomicAdd(&hist[descs[e.prob[i]].acc_off + (uint64_t)e.k0[i]], 1u);
+}
+
+__global__ void fill_i32_kernel(int32_t* __restrict__ p, int32_t v, uint64_t n) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 __global__ void copy_u32_kernel(const uint32_t* __restrict__ a, uint32_t* __restrict__ b,
@@ -176,15 +192,14 @@ __global__ void copy_u32_kernel(const uint32_t* __restrict__ a, uint32_t* __rest
   if (i < n) b[i] = a[i];
 }
 
-__global__ void scatter_kernel(const Desc* __restrict__ descs, int n_prob,
-                               const uint64_t* __restrict__ slot_off, uint64_t n_slots,
-                               uint32_t* __restrict__ cursor, EnsPtrs e) {
+__global__ void scatter_kernel(const Desc* __restrict__ descs, uint64_t n_slots,
+                               uint32_t* __restrict__ cursor, EnsPtrs e,
+                               const int32_t* __restrict__ select, uint32_t* __restrict__ order) {
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_slots) return;
-  if (!(e.w[i] > 0.0)) return;
+  if (i >= n_slots || !selected(e, select, i)) return;
   const Desc& d = descs[e.prob[i]];
   uint32_t pos = atomicAdd(&cursor[d.acc_off + (uint64_t)e.k0[i]], 1u);
-  e.order[pos] = (uint32_t)i;
+  order[pos] = (uint32_t)i;
 }
 
 // Within each bin the scatter order is arbitrary; sort every bin's slots
@@ -280,18 +295,32 @@ hipError_t launch_sample(const Desc* descs, int n_prob, const uint64_t* slot_off
   return hipGetLastError();
 }
 
-hipError_t launch_sort(const Desc* descs, int n_prob, const uint64_t* slot_off, uint64_t n_slots,
-                       uint64_t n_bins, uint32_t* hist, uint32_t* cursor, EnsPtrs e,
-                       hipStream_t s) {
+hipError_t launch_count(const Desc* descs, uint64_t n_slots, EnsPtrs e, const int32_t* select,
+                        uint32_t* hist, hipStream_t s) {
+  if (n_slots == 0) return hipSuccess;
+  hipLaunchKernelGGL(count_kernel, dim3(blocks_for(n_slots, kBlock)), dim3(kBlock), 0, s, descs,
+                     n_slots, e, select, hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, uint64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort(const Desc* descs, int n_prob, uint64_t n_slots, uint64_t n_bins,
+                       uint32_t* hist, uint32_t* cursor, EnsPtrs e, const int32_t* select,
+                       PackOut out, hipStream_t s) {
   hipLaunchKernelGGL(scan_bins_kernel, dim3(1), dim3(1024), 0, s, hist, n_bins);
-  hipLaunchKernelGGL(problem_runs_kernel, dim3(1), dim3(64), 0, s, descs, n_prob, hist, e);
+  hipLaunchKernelGGL(problem_runs_kernel, dim3(1), dim3(64), 0, s, descs, n_prob, hist, out);
   hipLaunchKernelGGL(copy_u32_kernel, dim3(blocks_for(n_bins + 1, kBlock)), dim3(kBlock), 0, s,
                      hist, cursor, n_bins + 1);
   if (n_slots > 0)
     hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(n_slots, kBlock)), dim3(kBlock), 0, s,
-                       descs, n_prob, slot_off, n_slots, cursor, e);
+                       descs, n_slots, cursor, e, select, out.order);
   hipLaunchKernelGGL(sort_bins_kernel, dim3(blocks_for(n_bins, kBlock)), dim3(kBlock), 0, s, hist,
-                     n_bins, e.order);
+                     n_bins, out.order);
   return hipGetLastError();
 }
 

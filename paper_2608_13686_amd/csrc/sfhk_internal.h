@@ -22,6 +22,7 @@ struct Desc {
   // target (Eq. 7) and coherent state
   double half_R, Ip, gamma, inv_gamma, inv_gamma2, half_inv_gamma;
   double Zinf[2], dZ[2], alpha[2], eps2[2];
+  float fZinf[2], fdZ[2], falpha[2], feps2[2];  // the same, rounded to FP32
   // sampling (first-order tunnel exit and amplitude weight)
   double sigma, w_cut, kappa, wpow, kcube3, inv_E0;
   double nfix[3];
@@ -35,6 +36,7 @@ struct Desc {
   double g_sgn[SFHK_MAX_GTO], g_inv4k[SFHK_MAX_GTO], g_inv2k[SFHK_MAX_GTO];
   double g_norm[SFHK_MAX_GTO], g_i2a[SFHK_MAX_GTO];
   int32_t g_l[SFHK_MAX_GTO];
+  double g_inv4k_min;  // smallest 1/(4 kappa2) over the primitives
 };
 
 // Device pointers of the ensemble, passed by value to kernels.
@@ -52,6 +54,9 @@ struct Workspace {
   double* field;        // [sum 2 (N_P + 1)]
   uint32_t* hist;       // [n_bins + 1] counting-sort bins (then bin starts)
   uint32_t* cursor;     // [n_bins + 1]
+  int32_t* redo;        // [capacity] mixed precision: FP64 re-run from this step (-1: none)
+  uint32_t* order2;     // [capacity] packs of the FP64 re-run
+  uint32_t* runs2;      // [3 n_prob + 1] live_start, live_count, pack_start of the re-run
   size_t bytes;
 };
 
@@ -61,7 +66,18 @@ struct Layout {
   uint64_t n_slots = 0;       // sum n_per_prob (sampling) or capacity
   size_t bytes = 0;
   size_t off_descs = 0, off_slot = 0, off_field = 0, off_hist = 0, off_cursor = 0;
+  size_t off_redo = 0, off_order2 = 0, off_runs2 = 0;
 };
+
+// Outputs of the counting sort into 64-lane packs.
+struct PackOut {
+  uint32_t *order, *live_start, *live_count, *pack_start;
+};
+
+// The mixed-precision kernel hands a trajectory to the FP64 kernel once an
+// entry of its FP32 monodromy matrix exceeds this bound (FP32 rounding is
+// then amplified past ~6e-4 relative).
+constexpr float kMixedFlagNorm = 1.0e4f;
 
 // launchers (setup_kernels.hip)
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
@@ -70,16 +86,26 @@ hipError_t launch_field(const Desc* descs, int n_prob, double* field, uint64_t n
 hipError_t launch_sample(const Desc* descs, int n_prob, const uint64_t* slot_off,
                          uint64_t n_slots, const double* field, EnsPtrs e, uint32_t* hist,
                          hipStream_t s);
-hipError_t launch_sort(const Desc* descs, int n_prob, const uint64_t* slot_off, uint64_t n_slots,
-                       uint64_t n_bins, uint32_t* hist, uint32_t* cursor, EnsPtrs e,
-                       hipStream_t s);
+// Counts slot i (select ? select[i] >= 0 : w[i] > 0) into bin acc_off[prob] + k0.
+hipError_t launch_count(const Desc* descs, uint64_t n_slots, EnsPtrs e, const int32_t* select,
+                        uint32_t* hist, hipStream_t s);
+// Counting sort of the selected slots by (problem, k0, slot) into packs.
+hipError_t launch_sort(const Desc* descs, int n_prob, uint64_t n_slots, uint64_t n_bins,
+                       uint32_t* hist, uint32_t* cursor, EnsPtrs e, const int32_t* select,
+                       PackOut out, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, uint64_t n, hipStream_t s);
 hipError_t launch_scale(const double* in, double* out, double scale, uint64_t n, hipStream_t s);
 hipError_t launch_spectrum(const double* v, int n_t, double t_first, double dt, double tau_H,
                            const double* omega, int n_omega, double* V_re, double* V_im,
                            double* yield, hipStream_t s);
-// propagate_f64.hip
+// propagate_f64.hip, propagate_mixed.hip
+// dep_from (nullable, per slot): deposit amplitudes only from that step on.
 hipError_t launch_propagate_f64(const Desc* descs, int n_prob, const double* field, EnsPtrs e,
-                                uint32_t max_packs, double* accum, double* final_state,
-                                uint64_t capacity, hipStream_t s);
+                                const int32_t* dep_from, uint32_t max_packs, double* accum,
+                                double* final_state, uint64_t capacity, hipStream_t s);
+// redo (per slot, preset to -1): set to the first step left to the FP64 re-run.
+hipError_t launch_propagate_mixed(const Desc* descs, int n_prob, const double* field, EnsPtrs e,
+                                  int32_t* redo, uint32_t max_packs, double* accum,
+                                  double* final_state, uint64_t capacity, hipStream_t s);
 
 }  // namespace sfhk
