@@ -202,6 +202,60 @@ sfhk_status sfhk_spectrum(const double* v, int32_t n_t, double t_first, double d
                           const double* omega, int32_t n_omega, double* V_re, double* V_im,
                           double* yield, void* stream);
 
+/* ------------------------------------------------------------------ plans
+ * A plan runs the whole path -- sampling, packing, propagation, dipole and
+ * spectrum -- for a batch of problems (alignments, intensities, CEPs, targets;
+ * Eq. 5-6 averaging is a sum over such problems or over sampled axes) with one
+ * enqueue, or as one recorded HIP graph.  The plan is a host object that
+ * keeps pointers to caller-owned device memory; it allocates no device
+ * memory.  Calls on one plan must not overlap. */
+
+/* Launch options of the trajectory kernels (chosen by the autotuner). */
+typedef struct {
+  int32_t persistent;    /* 0: one wavefront per 64-lane pack, packs in (problem, birth) order;
+                            1: a persistent grid pulls packs, longest first, from a device queue */
+  int32_t waves_per_cu;  /* persistent grid = 256 CUs x waves_per_cu wavefronts, 1..32 (0: 8) */
+  int32_t step_unroll;   /* RK4 steps per loop trip: 1 or 2 (0: 1) */
+  int32_t traj_per_lane; /* trajectories per lane: 1 (0: 1); the FP64 state of one trajectory
+                            already fills the register budget of two wavefronts per SIMD */
+} sfhk_tuning;
+
+typedef struct sfhk_plan sfhk_plan;
+
+/* Host only.  Device workspace bytes of a plan. */
+size_t sfhk_plan_workspace_bytes(const sfhk_problem* probs, int32_t n_prob,
+                                 const uint64_t* n_per_prob);
+
+/* Create a plan and enqueue its set-up (problem tables) on `stream`.
+ *   probs, n_per_prob, seeds, first_index: host [n_prob], as sfhk_sample_initial;
+ *   precision: SFHK_FP64 or SFHK_MIXED; tuning: NULL for the defaults;
+ *   spectra on each problem's harmonic grid w_m = m h_step w_laser, m < n_omega;
+ *   ens: device ensemble, capacity >= sum(n_per_prob);
+ *   workspace: device, >= sfhk_plan_workspace_bytes;
+ *   accum, v: device double [sum_P (N_P + 1)] (accum layout of sfhk_propagate);
+ *   V_re, V_im, yield: device double [n_prob][n_omega].
+ * Every run overwrites accum, v and the spectra (v = 2 accum / n_per_prob[P]). */
+sfhk_status sfhk_plan_create(const sfhk_problem* probs, int32_t n_prob,
+                             const uint64_t* n_per_prob, const uint64_t* seeds,
+                             const uint64_t* first_index, int32_t precision,
+                             const sfhk_tuning* tuning, double h_step, int32_t n_omega,
+                             const sfhk_ensemble* ens, void* workspace, size_t workspace_bytes,
+                             double* accum, double* v, double* V_re, double* V_im, double* yield,
+                             void* stream, sfhk_plan** plan);
+
+/* Enqueue the whole path on `stream`. */
+sfhk_status sfhk_plan_run(sfhk_plan* plan, void* stream);
+
+/* Record sfhk_plan_run into a HIP graph (stream must not be the null stream);
+ * nothing is executed.  Replaces an earlier recording. */
+sfhk_status sfhk_plan_capture(sfhk_plan* plan, void* stream);
+
+/* Launch the recorded graph on `stream` (SFHK_E_INVALID if none). */
+sfhk_status sfhk_plan_replay(sfhk_plan* plan, void* stream);
+
+/* Release the plan and its graph (host resources only). */
+void sfhk_plan_destroy(sfhk_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

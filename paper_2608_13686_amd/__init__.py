@@ -13,7 +13,8 @@ from . import _abi
 from ._abi import FS_COUNT, FS_CIM, FS_CRE, FS_FLIPS, FS_M, FS_P, FS_Q, FS_S, SfhkError
 
 __all__ = ["problem_steps", "workspace_bytes", "Ensemble", "sample_initial", "propagate",
-           "dipole", "spectrum", "run", "SfhkError", "harmonic_grid", "abi_version"]
+           "dipole", "spectrum", "run", "SfhkError", "harmonic_grid", "abi_version", "Plan",
+           "accum_layout"]
 
 PRECISION = {"fp64": _abi.FP64, "mixed": _abi.MIXED}
 
@@ -183,3 +184,78 @@ def run(probs, n_traj, seeds, precision="fp64", h_max=40.0, device="cuda", strea
         out["omega"].append(om)
         out["t_first"].append(t0)
     return out
+
+
+class Plan:
+    """The whole path for a batch of problems behind one plan (sfhk_plan_*):
+    ``run()`` enqueues sampling, packing, propagation, dipole and spectra;
+    ``capture(stream)`` records the same into a HIP graph that ``replay()``
+    launches.  Outputs (overwritten by every run): ``accum``, ``v`` (accum
+    layout), ``V`` and ``yield_`` ([n_prob, n_omega] on each problem's
+    harmonic grid h = 0, h_step, ..., h_max)."""
+
+    def __init__(self, probs, n_traj, seeds, precision="fp64", tuning=None, h_max=40.0,
+                 h_step=0.05, first_index=None, device="cuda", stream=None):
+        self.probs = list(probs)
+        n_prob = len(self.probs)
+        self.n_traj = [int(n) for n in n_traj]
+        self.first_index = [0] * n_prob if first_index is None else list(first_index)
+        self.n_omega = int(round(h_max / h_step)) + 1
+        self.h_step = h_step
+        self._arr = _abi.make_problems(self.probs)
+        L = _abi.lib()
+        nb = L.sfhk_plan_workspace_bytes(self._arr, n_prob, _abi.u64_array(self.n_traj))
+        if nb == 0:
+            raise SfhkError(1, "sfhk_plan_workspace_bytes")
+        self.ens = Ensemble(sum(self.n_traj), n_prob, device)
+        self.workspace = torch.empty(nb, dtype=torch.uint8, device=device)
+        self.offsets, self.lengths = accum_layout(self.probs)
+        n_acc = sum(self.lengths)
+        self.accum = torch.zeros(n_acc, dtype=torch.float64, device=device)
+        self.v = torch.zeros(n_acc, dtype=torch.float64, device=device)
+        self.V_re = torch.zeros((n_prob, self.n_omega), dtype=torch.float64, device=device)
+        self.V_im = torch.zeros_like(self.V_re)
+        self.yield_ = torch.zeros_like(self.V_re)
+        t = _abi.Tuning(*(tuning or (0, 8, 1, 1)))
+        es = self.ens.struct()
+        h = C.c_void_p()
+        _abi.check(L.sfhk_plan_create(
+            self._arr, n_prob, _abi.u64_array(self.n_traj), _abi.u64_array(seeds),
+            _abi.u64_array(self.first_index), PRECISION[precision], C.byref(t), float(h_step),
+            self.n_omega, C.byref(es), C.c_void_p(self.workspace.data_ptr()),
+            self.workspace.numel(), C.c_void_p(self.accum.data_ptr()),
+            C.c_void_p(self.v.data_ptr()), C.c_void_p(self.V_re.data_ptr()),
+            C.c_void_p(self.V_im.data_ptr()), C.c_void_p(self.yield_.data_ptr()),
+            _stream(stream), C.byref(h)), "sfhk_plan_create")
+        self._h = h
+
+    def run(self, stream=None):
+        _abi.check(_abi.lib().sfhk_plan_run(self._h, _stream(stream)), "sfhk_plan_run")
+
+    def capture(self, stream):
+        """Record run() into a HIP graph on a non-default torch stream."""
+        _abi.check(_abi.lib().sfhk_plan_capture(self._h, _stream(stream)), "sfhk_plan_capture")
+
+    def replay(self, stream=None):
+        _abi.check(_abi.lib().sfhk_plan_replay(self._h, _stream(stream)), "sfhk_plan_replay")
+
+    @property
+    def V(self):
+        return torch.complex(self.V_re, self.V_im)
+
+    def v_of(self, i):
+        return self.v[self.offsets[i]:self.offsets[i] + self.lengths[i]]
+
+    def omega(self, i):
+        return harmonic_grid(self.probs[i], (self.n_omega - 1) * self.h_step, self.h_step)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _abi.lib().sfhk_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

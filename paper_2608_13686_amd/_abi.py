@@ -13,7 +13,9 @@ STATUS = {0: "SFHK_OK", 1: "SFHK_E_INVALID", 2: "SFHK_E_NOMEM", 3: "SFHK_E_DEVIC
           4: "SFHK_E_BUSY", 5: "SFHK_E_UNSUPPORTED"}
 
 EXPORTS = ["sfhk_abi_version", "sfhk_last_error", "sfhk_problem_steps", "sfhk_workspace_bytes",
-           "sfhk_sample_initial", "sfhk_propagate", "sfhk_dipole", "sfhk_spectrum"]
+           "sfhk_sample_initial", "sfhk_propagate", "sfhk_dipole", "sfhk_spectrum",
+           "sfhk_plan_workspace_bytes", "sfhk_plan_create", "sfhk_plan_run", "sfhk_plan_capture",
+           "sfhk_plan_replay", "sfhk_plan_destroy"]
 
 
 class Center(C.Structure):
@@ -55,6 +57,11 @@ class Ensemble(C.Structure):
                 ("pack_start", C.c_void_p)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("persistent", C.c_int32), ("waves_per_cu", C.c_int32),
+                ("step_unroll", C.c_int32), ("traj_per_lane", C.c_int32)]
+
+
 _lib = None
 
 
@@ -88,6 +95,19 @@ def lib():
                                     C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p]
         L.sfhk_spectrum.restype = C.c_int
+        L.sfhk_plan_workspace_bytes.argtypes = [P, C.c_int32, u64p]
+        L.sfhk_plan_workspace_bytes.restype = C.c_size_t
+        L.sfhk_plan_create.argtypes = [P, C.c_int32, u64p, u64p, u64p, C.c_int32,
+                                       C.POINTER(Tuning), C.c_double, C.c_int32,
+                                       C.POINTER(Ensemble), C.c_void_p, C.c_size_t, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.POINTER(C.c_void_p)]
+        L.sfhk_plan_create.restype = C.c_int
+        for f in ("sfhk_plan_run", "sfhk_plan_capture", "sfhk_plan_replay"):
+            getattr(L, f).argtypes = [C.c_void_p, C.c_void_p]
+            getattr(L, f).restype = C.c_int
+        L.sfhk_plan_destroy.argtypes = [C.c_void_p]
+        L.sfhk_plan_destroy.restype = None
         _lib = L
     return _lib
 

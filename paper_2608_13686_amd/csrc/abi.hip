@@ -6,6 +6,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <memory>
+#include <new>
 #include <vector>
 
 #include "sfhk_internal.h"
@@ -174,7 +176,7 @@ Desc make_desc(const sfhk_problem& p) {
 
 // Descriptors with field/accum offsets; returns the layout.
 Layout build_layout(const sfhk_problem* probs, int32_t n_prob, uint64_t n_slots,
-                    std::vector<Desc>* descs, int64_t* max_steps) {
+                    std::vector<Desc>* descs, int64_t* max_steps, bool with_queue = false) {
   Layout L;
   uint64_t fo = 0, ao = 0;
   int64_t mx = 0;
@@ -212,6 +214,22 @@ Layout build_layout(const sfhk_problem* probs, int32_t n_prob, uint64_t n_slots,
   off = align256(off + sizeof(uint32_t) * (size_t)n_slots);
   L.off_runs2 = off;
   off = align256(off + sizeof(uint32_t) * (3 * (size_t)n_prob + 1));
+  if (with_queue) {
+    L.max_packs = (uint32_t)((n_slots + kWave - 1) / kWave + (uint64_t)n_prob);
+    L.n_len = (uint32_t)(mx + 1);
+    L.off_qkeys = off;
+    off = align256(off + sizeof(uint32_t) * (size_t)L.max_packs);
+    L.off_qhist = off;
+    off = align256(off + sizeof(uint32_t) * ((size_t)L.n_len + 1));
+    L.off_qcursor = off;
+    off = align256(off + sizeof(uint32_t) * ((size_t)L.n_len + 1));
+    L.off_queue = off;
+    off = align256(off + sizeof(uint32_t) * (size_t)L.max_packs);
+    L.off_queue2 = off;
+    off = align256(off + sizeof(uint32_t) * (size_t)L.max_packs);
+    L.off_counter = off;
+    off = align256(off + 2 * sizeof(uint32_t));
+  }
   L.bytes = off;
   if (max_steps) *max_steps = mx;
   return L;
@@ -383,7 +401,7 @@ sfhk_status sfhk_propagate(const sfhk_problem* probs, int32_t n_prob, const sfhk
   hipError_t e;
   if (precision == SFHK_FP64) {
     e = launch_propagate_f64(ws.descs, n_prob, ws.field, ep, nullptr, (uint32_t)max_packs, accum,
-                             final_state, ens->capacity, s);
+                             final_state, ens->capacity, s, LaunchCfg{});
   } else {
     // FP32 stepping for every trajectory; those whose monodromy matrix grows
     // past the FP32 bound are handed over, at that step, to an FP64 re-run
@@ -391,7 +409,7 @@ sfhk_status sfhk_propagate(const sfhk_problem* probs, int32_t n_prob, const sfhk
     e = launch_fill_i32(ws.redo, -1, ens->capacity, s);
     if (e == hipSuccess)
       e = launch_propagate_mixed(ws.descs, n_prob, ws.field, ep, ws.redo, (uint32_t)max_packs,
-                                 accum, final_state, ens->capacity, s);
+                                 accum, final_state, ens->capacity, s, LaunchCfg{});
     if (e == hipSuccess) e = launch_fill_u32(ws.hist, 0u, L.n_bins + 1, s);
     if (e == hipSuccess) e = launch_count(ws.descs, ens->capacity, ep, ws.redo, ws.hist, s);
     PackOut po{ws.order2, ws.runs2, ws.runs2 + n_prob, ws.runs2 + 2 * n_prob};
@@ -405,7 +423,7 @@ sfhk_status sfhk_propagate(const sfhk_problem* probs, int32_t n_prob, const sfhk
       e2.live_count = po.live_count;
       e2.pack_start = po.pack_start;
       e = launch_propagate_f64(ws.descs, n_prob, ws.field, e2, ws.redo, (uint32_t)max_packs,
-                               accum, final_state, ens->capacity, s);
+                               accum, final_state, ens->capacity, s, LaunchCfg{});
     }
   }
   if (e != hipSuccess) return hip_fail(e, "propagate");
@@ -446,6 +464,251 @@ sfhk_status sfhk_spectrum(const double* v, int32_t n_t, double t_first, double d
                                  static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "spectrum");
   return ok();
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ plans
+
+struct sfhk_plan {
+  int n_prob = 0;
+  int precision = SFHK_FP64;
+  sfhk_tuning tune{};
+  std::vector<Desc> descs;
+  Layout L;
+  Workspace ws{};
+  EnsPtrs ens{};
+  uint64_t capacity = 0, n_slots = 0;
+  int64_t max_steps = 0;
+  uint32_t grid = 0;
+  double *accum = nullptr, *v = nullptr, *Vre = nullptr, *Vim = nullptr, *Y = nullptr;
+  double h_step = 0.0;
+  int n_omega = 0;
+  uint32_t *qkeys = nullptr, *qhist = nullptr, *qcursor = nullptr, *queue = nullptr,
+           *queue2 = nullptr, *counter = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+sfhk_status plan_enqueue(sfhk_plan* P, hipStream_t s) {
+  const int n_prob = P->n_prob;
+  const Workspace& ws = P->ws;
+  EnsPtrs ep = P->ens;
+  LaunchCfg cfg;
+  cfg.persistent = P->tune.persistent;
+  cfg.unroll = P->tune.step_unroll;
+  cfg.grid = P->grid;
+  cfg.queue = P->queue;
+  cfg.counter = P->counter;
+  const uint32_t mp = P->L.max_packs;
+  hipError_t e = launch_fill_u32(ws.hist, 0u, P->L.n_bins + 1, s);
+  if (e == hipSuccess)
+    e = launch_sample(ws.descs, n_prob, ws.slot_off, P->n_slots, ws.field, ep, ws.hist, s);
+  PackOut po{ep.order, ep.live_start, ep.live_count, ep.pack_start};
+  if (e == hipSuccess)
+    e = launch_sort(ws.descs, n_prob, P->n_slots, P->L.n_bins, ws.hist, ws.cursor, ep, nullptr,
+                    po, s);
+  if (e == hipSuccess) e = launch_fill_f64(P->accum, 0.0, P->L.n_bins, s);
+  if (e == hipSuccess && cfg.persistent) {
+    e = launch_pack_queue(ws.descs, n_prob, ep, mp, P->L.n_len, P->qkeys, P->qhist, P->qcursor,
+                          P->queue, s);
+    if (e == hipSuccess) e = launch_fill_u32(P->counter, 0u, 2, s);
+  }
+  if (e == hipSuccess) {
+    if (P->precision == SFHK_FP64) {
+      e = launch_propagate_f64(ws.descs, n_prob, ws.field, ep, nullptr, mp, P->accum, nullptr,
+                               P->capacity, s, cfg);
+    } else {
+      e = launch_fill_i32(ws.redo, -1, P->capacity, s);
+      if (e == hipSuccess)
+        e = launch_propagate_mixed(ws.descs, n_prob, ws.field, ep, ws.redo, mp, P->accum,
+                                   nullptr, P->capacity, s, cfg);
+      if (e == hipSuccess) e = launch_fill_u32(ws.hist, 0u, P->L.n_bins + 1, s);
+      if (e == hipSuccess) e = launch_count(ws.descs, P->n_slots, ep, ws.redo, ws.hist, s);
+      PackOut p2{ws.order2, ws.runs2, ws.runs2 + n_prob, ws.runs2 + 2 * n_prob};
+      if (e == hipSuccess)
+        e = launch_sort(ws.descs, n_prob, P->n_slots, P->L.n_bins, ws.hist, ws.cursor, ep,
+                        ws.redo, p2, s);
+      EnsPtrs e2 = ep;
+      e2.order = p2.order;
+      e2.live_start = p2.live_start;
+      e2.live_count = p2.live_count;
+      e2.pack_start = p2.pack_start;
+      LaunchCfg cfg2 = cfg;
+      cfg2.queue = P->queue2;
+      cfg2.counter = P->counter + 1;
+      if (e == hipSuccess && cfg.persistent)
+        e = launch_pack_queue(ws.descs, n_prob, e2, mp, P->L.n_len, P->qkeys, P->qhist,
+                              P->qcursor, P->queue2, s);
+      if (e == hipSuccess)
+        e = launch_propagate_f64(ws.descs, n_prob, ws.field, e2, ws.redo, mp, P->accum, nullptr,
+                                 P->capacity, s, cfg2);
+    }
+  }
+  if (e == hipSuccess)
+    e = launch_dipole_batched(ws.descs, n_prob, (uint32_t)(P->max_steps + 1), P->accum, P->v, s);
+  if (e == hipSuccess)
+    e = launch_spectrum_batched(ws.descs, n_prob, P->v, P->h_step, P->n_omega, P->Vre, P->Vim,
+                                P->Y, s);
+  if (e != hipSuccess) return hip_fail(e, "plan run");
+  return SFHK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sfhk_plan_workspace_bytes(const sfhk_problem* probs, int32_t n_prob,
+                                 const uint64_t* n_per_prob) {
+  if (check_problems(probs, n_prob) != SFHK_OK || !n_per_prob) return 0;
+  uint64_t n = 0;
+  for (int i = 0; i < n_prob; ++i) n += n_per_prob[i];
+  g_err.clear();
+  return build_layout(probs, n_prob, n, nullptr, nullptr, true).bytes;
+}
+
+sfhk_status sfhk_plan_create(const sfhk_problem* probs, int32_t n_prob,
+                             const uint64_t* n_per_prob, const uint64_t* seeds,
+                             const uint64_t* first_index, int32_t precision,
+                             const sfhk_tuning* tuning, double h_step, int32_t n_omega,
+                             const sfhk_ensemble* ens, void* workspace, size_t workspace_bytes,
+                             double* accum, double* v, double* V_re, double* V_im, double* yield,
+                             void* stream, sfhk_plan** plan) {
+  sfhk_status st = check_problems(probs, n_prob);
+  if (st != SFHK_OK) return st;
+  if (!plan) return fail(SFHK_E_INVALID, "plan is null");
+  *plan = nullptr;
+  if (!n_per_prob || !seeds || !first_index)
+    return fail(SFHK_E_INVALID, "n_per_prob, seeds and first_index must be non-null");
+  if (precision != SFHK_FP64 && precision != SFHK_MIXED)
+    return fail(SFHK_E_INVALID, "unknown precision %d", precision);
+  if ((st = check_ensemble(ens)) != SFHK_OK) return st;
+  if (!accum || !v) return fail(SFHK_E_INVALID, "accum and v must be non-null");
+  if (n_omega < 0 || (n_omega > 0 && (!V_re || !V_im || !yield || !(h_step >= 0.0))))
+    return fail(SFHK_E_INVALID, "spectrum outputs invalid");
+  sfhk_tuning t{0, 8, 1, 1};
+  if (tuning) {
+    t = *tuning;
+    if (t.waves_per_cu == 0) t.waves_per_cu = 8;
+    if (t.step_unroll == 0) t.step_unroll = 1;
+    if (t.traj_per_lane == 0) t.traj_per_lane = 1;
+  }
+  if ((t.persistent != 0 && t.persistent != 1) || t.waves_per_cu < 1 || t.waves_per_cu > 32 ||
+      (t.step_unroll != 1 && t.step_unroll != 2))
+    return fail(SFHK_E_INVALID, "tuning out of range");
+  if (t.traj_per_lane != 1)
+    return fail(SFHK_E_UNSUPPORTED, "traj_per_lane %d: only 1 fits the register budget",
+                t.traj_per_lane);
+  std::vector<uint64_t> slot_off(n_prob + 1, 0);
+  for (int i = 0; i < n_prob; ++i) {
+    if (n_per_prob[i] > (uint64_t(1) << 32))
+      return fail(SFHK_E_INVALID, "n_per_prob[%d] too large", i);
+    slot_off[i + 1] = slot_off[i] + n_per_prob[i];
+  }
+  const uint64_t n_slots = slot_off[n_prob];
+  if (n_slots > ens->capacity)
+    return fail(SFHK_E_NOMEM, "sum(n_per_prob) exceeds ensemble capacity");
+  std::unique_ptr<sfhk_plan> P(new (std::nothrow) sfhk_plan());
+  if (!P) return fail(SFHK_E_NOMEM, "host allocation of the plan failed");
+  P->L = build_layout(probs, n_prob, n_slots, &P->descs, &P->max_steps, true);
+  if (P->L.n_bins + 1 >= (uint64_t(1) << 31))
+    return fail(SFHK_E_UNSUPPORTED, "total step count of the problems too large");
+  if (!workspace) return fail(SFHK_E_INVALID, "workspace is null");
+  if (workspace_bytes < P->L.bytes)
+    return fail(SFHK_E_NOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, P->L.bytes);
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(e, "device query");
+  for (int i = 0; i < n_prob; ++i) {
+    P->descs[i].slot_off = slot_off[i];
+    P->descs[i].n_slots = n_per_prob[i];
+    P->descs[i].seed = seeds[i];
+    P->descs[i].first_index = first_index[i];
+  }
+  P->n_prob = n_prob;
+  P->precision = precision;
+  P->tune = t;
+  P->ws = carve(workspace, P->L);
+  P->ens = ens_ptrs(ens);
+  P->capacity = ens->capacity;
+  P->n_slots = n_slots;
+  P->grid = (uint32_t)cus * (uint32_t)t.waves_per_cu;
+  P->accum = accum;
+  P->v = v;
+  P->Vre = V_re;
+  P->Vim = V_im;
+  P->Y = yield;
+  P->h_step = h_step;
+  P->n_omega = n_omega;
+  char* b = static_cast<char*>(workspace);
+  P->qkeys = reinterpret_cast<uint32_t*>(b + P->L.off_qkeys);
+  P->qhist = reinterpret_cast<uint32_t*>(b + P->L.off_qhist);
+  P->qcursor = reinterpret_cast<uint32_t*>(b + P->L.off_qcursor);
+  P->queue = reinterpret_cast<uint32_t*>(b + P->L.off_queue);
+  P->queue2 = reinterpret_cast<uint32_t*>(b + P->L.off_queue2);
+  P->counter = reinterpret_cast<uint32_t*>(b + P->L.off_counter);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = stage_problems(P->descs, P->ws, &slot_off, P->max_steps, s)) != SFHK_OK) return st;
+  // the host copy of the descriptors must outlive the asynchronous upload
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "plan set-up");
+  *plan = P.release();
+  return ok();
+}
+
+sfhk_status sfhk_plan_run(sfhk_plan* plan, void* stream) {
+  if (!plan) return fail(SFHK_E_INVALID, "plan is null");
+  sfhk_status st = plan_enqueue(plan, static_cast<hipStream_t>(stream));
+  return st == SFHK_OK ? ok() : st;
+}
+
+sfhk_status sfhk_plan_capture(sfhk_plan* plan, void* stream) {
+  if (!plan) return fail(SFHK_E_INVALID, "plan is null");
+  if (!stream) return fail(SFHK_E_INVALID, "graph capture needs a non-null stream");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (plan->exec) {
+    hipGraphExecDestroy(plan->exec);
+    plan->exec = nullptr;
+  }
+  if (plan->graph) {
+    hipGraphDestroy(plan->graph);
+    plan->graph = nullptr;
+  }
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "begin capture");
+  sfhk_status st = plan_enqueue(plan, s);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(s, &g);
+  if (st != SFHK_OK) {
+    if (g) hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "end capture");
+  e = hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    hipGraphDestroy(g);
+    return hip_fail(e, "graph instantiate");
+  }
+  plan->graph = g;
+  return ok();
+}
+
+sfhk_status sfhk_plan_replay(sfhk_plan* plan, void* stream) {
+  if (!plan) return fail(SFHK_E_INVALID, "plan is null");
+  if (!plan->exec) return fail(SFHK_E_INVALID, "plan has no recorded graph");
+  hipError_t e = hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
+  return ok();
+}
+
+void sfhk_plan_destroy(sfhk_plan* plan) {
+  if (!plan) return;
+  if (plan->exec) hipGraphExecDestroy(plan->exec);
+  if (plan->graph) hipGraphDestroy(plan->graph);
+  delete plan;
 }
 
 }  // extern "C"

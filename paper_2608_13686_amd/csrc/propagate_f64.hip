@@ -16,20 +16,20 @@ namespace {
 // of a wavefront touches 64 consecutive doubles.
 constexpr int kMonoElems = 36;  // row-major 6x6, rows (q, p), columns (q0, p0)
 
-__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2)))
-propagate_f64_kernel(const Desc* __restrict__ descs, int n_prob, const double* __restrict__ field,
-                     EnsPtrs e, const int32_t* __restrict__ dep_from, double* __restrict__ accum,
-                     double* __restrict__ final_state, uint64_t capacity) {
-  __shared__ double mono[kMonoElems][kWave];
-  const int lane = threadIdx.x;
-  Pack pk;
-  if (!find_pack(e, n_prob, blockIdx.x, lane, pk)) return;
+// One 64-lane pack: every live lane runs its trajectory from its birth step
+// to t_N.  U consecutive steps are unrolled per loop trip.
+template <int U>
+__device__ __forceinline__ void run_pack(const Desc* __restrict__ descs,
+                                         const double* __restrict__ field, const EnsPtrs& e,
+                                         const int32_t* __restrict__ dep_from,
+                                         double* __restrict__ accum,
+                                         double* __restrict__ final_state, uint64_t capacity,
+                                         const Pack& pk, int lane, double (*mono)[kWave]) {
   const Desc& d = descs[pk.prob];
   const int N = d.N;
   const bool valid = pk.valid;
   const uint32_t slot = pk.slot;
 
-  // initial conditions
   const int k0 = valid ? e.k0[slot] : N + 1;
   // amplitudes are deposited from step kdep on (the re-run of a trajectory
   // that the mixed-precision kernel handed over deposits only its remainder)
@@ -61,7 +61,11 @@ propagate_f64_kernel(const Desc* __restrict__ descs, int n_prob, const double* _
   const int kmin = __builtin_amdgcn_readfirstlane(k0);
   double acc_reg = 0.0;
 
-  for (int k = kmin;; ++k) {
+  for (int kc = kmin; kc <= N; kc += U) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = kc + u;
+    if (k > N) break;
     const bool live = k >= k0;
     double re_a = 0.0;
     if (live) {
@@ -70,8 +74,7 @@ propagate_f64_kernel(const Desc* __restrict__ descs, int n_prob, const double* _
         re_a = amplitude_re(d, n, p, q, Cre, Cim, S, d.t_first + (double)k * h, t0, p0q0, w);
     }
     deposit(re_a, k, N, lane, acc_reg, acc);
-    if (k >= N) break;
-    if (!live) continue;
+    if (k >= N || !live) continue;
 
     // --- classical RK4 step t_k -> t_{k+1}
     const double Ek = fe[2 * k], Eh = fe[2 * k + 1], E1 = fe[2 * k + 2];
@@ -190,6 +193,7 @@ propagate_f64_kernel(const Desc* __restrict__ descs, int n_prob, const double* _
       }
     }
   }
+  }
 
   if (final_state != nullptr && valid) {
     double* f = final_state + slot;
@@ -208,14 +212,64 @@ propagate_f64_kernel(const Desc* __restrict__ descs, int n_prob, const double* _
   }
 }
 
+template <int U>
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2)))
+propagate_f64_kernel(const Desc* __restrict__ descs, int n_prob, const double* __restrict__ field,
+                     EnsPtrs e, const int32_t* __restrict__ dep_from, double* __restrict__ accum,
+                     double* __restrict__ final_state, uint64_t capacity) {
+  __shared__ double mono[kMonoElems][kWave];
+  const int lane = threadIdx.x;
+  Pack pk;
+  if (!find_pack(e, n_prob, blockIdx.x, lane, pk)) return;
+  run_pack<U>(descs, field, e, dep_from, accum, final_state, capacity, pk, lane, mono);
+}
+
+// Persistent form: a fixed grid of wavefronts pulls pack indices from
+// queue[] through an atomic counter until the queue is exhausted.
+template <int U>
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2)))
+propagate_f64_persistent(const Desc* __restrict__ descs, int n_prob,
+                         const double* __restrict__ field, EnsPtrs e,
+                         const int32_t* __restrict__ dep_from, double* __restrict__ accum,
+                         double* __restrict__ final_state, uint64_t capacity,
+                         const uint32_t* __restrict__ queue, uint32_t* __restrict__ counter) {
+  __shared__ double mono[kMonoElems][kWave];
+  const int lane = threadIdx.x;
+  const uint32_t total = e.pack_start[n_prob];
+  for (;;) {
+    uint32_t idx = 0;
+    if (lane == 0) idx = atomicAdd(counter, 1u);
+    idx = __builtin_amdgcn_readfirstlane(idx);
+    if (idx >= total) break;
+    Pack pk;
+    find_pack(e, n_prob, queue[idx], lane, pk);
+    run_pack<U>(descs, field, e, dep_from, accum, final_state, capacity, pk, lane, mono);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_propagate_f64(const Desc* descs, int n_prob, const double* field, EnsPtrs e,
                                 const int32_t* dep_from, uint32_t max_packs, double* accum,
-                                double* final_state, uint64_t capacity, hipStream_t s) {
+                                double* final_state, uint64_t capacity, hipStream_t s,
+                                const LaunchCfg& cfg) {
   if (max_packs == 0) return hipSuccess;
-  hipLaunchKernelGGL(propagate_f64_kernel, dim3(max_packs), dim3(kWave), 0, s, descs, n_prob,
-                     field, e, dep_from, accum, final_state, capacity);
+  if (cfg.persistent) {
+    if (cfg.unroll == 2)
+      hipLaunchKernelGGL(propagate_f64_persistent<2>, dim3(cfg.grid), dim3(kWave), 0, s, descs,
+                         n_prob, field, e, dep_from, accum, final_state, capacity, cfg.queue,
+                         cfg.counter);
+    else
+      hipLaunchKernelGGL(propagate_f64_persistent<1>, dim3(cfg.grid), dim3(kWave), 0, s, descs,
+                         n_prob, field, e, dep_from, accum, final_state, capacity, cfg.queue,
+                         cfg.counter);
+  } else if (cfg.unroll == 2) {
+    hipLaunchKernelGGL(propagate_f64_kernel<2>, dim3(max_packs), dim3(kWave), 0, s, descs, n_prob,
+                       field, e, dep_from, accum, final_state, capacity);
+  } else {
+    hipLaunchKernelGGL(propagate_f64_kernel<1>, dim3(max_packs), dim3(kWave), 0, s, descs, n_prob,
+                       field, e, dep_from, accum, final_state, capacity);
+  }
   return hipGetLastError();
 }
 

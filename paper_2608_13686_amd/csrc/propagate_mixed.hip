@@ -10,14 +10,13 @@
 namespace sfhk {
 namespace {
 
-__global__ void __launch_bounds__(kWave)
-propagate_mixed_kernel(const Desc* __restrict__ descs, int n_prob,
-                       const double* __restrict__ field, EnsPtrs e, int32_t* __restrict__ redo,
-                       double* __restrict__ accum, double* __restrict__ final_state,
-                       uint64_t capacity) {
-  const int lane = threadIdx.x;
-  Pack pk;
-  if (!find_pack(e, n_prob, blockIdx.x, lane, pk)) return;
+template <int U>
+__device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
+                                               const double* __restrict__ field,
+                                               const EnsPtrs& e, int32_t* __restrict__ redo,
+                                               double* __restrict__ accum,
+                                               double* __restrict__ final_state,
+                                               uint64_t capacity, const Pack& pk, int lane) {
   const Desc& d = descs[pk.prob];
   const int N = d.N;
   const bool valid = pk.valid;
@@ -55,7 +54,11 @@ propagate_mixed_kernel(const Desc* __restrict__ descs, int n_prob,
   double acc_reg = 0.0;
   int kend = N + 1;  // first step left to the FP64 re-run (N + 1: none)
 
-  for (int k = kmin;; ++k) {
+  for (int kc = kmin; kc <= N; kc += U) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = kc + u;
+    if (k > N) break;
     const bool live = k >= k0 && k < kend;
     double re_a = 0.0;
     if (live) {
@@ -78,8 +81,7 @@ propagate_mixed_kernel(const Desc* __restrict__ descs, int n_prob,
       re_a = amplitude_re(d, n, pd_, qd_, Cre, Cim, S, d.t_first + (double)k * hd, t0, p0q0, w);
     }
     deposit(re_a, k, N, lane, acc_reg, acc);
-    if (k >= N) break;
-    if (!live) continue;
+    if (k >= N || !live) continue;
 
     // --- classical RK4 step t_k -> t_{k+1}; (q, p, M) in FP32, S in FP64
     const float Ek = (float)fe[2 * k], Eh = (float)fe[2 * k + 1], E1 = (float)fe[2 * k + 2];
@@ -191,6 +193,7 @@ propagate_mixed_kernel(const Desc* __restrict__ descs, int n_prob,
       redo[slot] = kend;
     }
   }
+  }
 
   if (final_state != nullptr && valid && kend > N) {
     double* f = final_state + slot;
@@ -214,14 +217,61 @@ propagate_mixed_kernel(const Desc* __restrict__ descs, int n_prob,
   }
 }
 
+template <int U>
+__global__ void __launch_bounds__(kWave)
+propagate_mixed_kernel(const Desc* __restrict__ descs, int n_prob,
+                       const double* __restrict__ field, EnsPtrs e, int32_t* __restrict__ redo,
+                       double* __restrict__ accum, double* __restrict__ final_state,
+                       uint64_t capacity) {
+  const int lane = threadIdx.x;
+  Pack pk;
+  if (!find_pack(e, n_prob, blockIdx.x, lane, pk)) return;
+  run_pack_mixed<U>(descs, field, e, redo, accum, final_state, capacity, pk, lane);
+}
+
+template <int U>
+__global__ void __launch_bounds__(kWave)
+propagate_mixed_persistent(const Desc* __restrict__ descs, int n_prob,
+                           const double* __restrict__ field, EnsPtrs e,
+                           int32_t* __restrict__ redo, double* __restrict__ accum,
+                           double* __restrict__ final_state, uint64_t capacity,
+                           const uint32_t* __restrict__ queue, uint32_t* __restrict__ counter) {
+  const int lane = threadIdx.x;
+  const uint32_t total = e.pack_start[n_prob];
+  for (;;) {
+    uint32_t idx = 0;
+    if (lane == 0) idx = atomicAdd(counter, 1u);
+    idx = __builtin_amdgcn_readfirstlane(idx);
+    if (idx >= total) break;
+    Pack pk;
+    find_pack(e, n_prob, queue[idx], lane, pk);
+    run_pack_mixed<U>(descs, field, e, redo, accum, final_state, capacity, pk, lane);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_propagate_mixed(const Desc* descs, int n_prob, const double* field, EnsPtrs e,
                                   int32_t* redo, uint32_t max_packs, double* accum,
-                                  double* final_state, uint64_t capacity, hipStream_t s) {
+                                  double* final_state, uint64_t capacity, hipStream_t s,
+                                  const LaunchCfg& cfg) {
   if (max_packs == 0) return hipSuccess;
-  hipLaunchKernelGGL(propagate_mixed_kernel, dim3(max_packs), dim3(kWave), 0, s, descs, n_prob,
-                     field, e, redo, accum, final_state, capacity);
+  if (cfg.persistent) {
+    if (cfg.unroll == 2)
+      hipLaunchKernelGGL(propagate_mixed_persistent<2>, dim3(cfg.grid), dim3(kWave), 0, s, descs,
+                         n_prob, field, e, redo, accum, final_state, capacity, cfg.queue,
+                         cfg.counter);
+    else
+      hipLaunchKernelGGL(propagate_mixed_persistent<1>, dim3(cfg.grid), dim3(kWave), 0, s, descs,
+                         n_prob, field, e, redo, accum, final_state, capacity, cfg.queue,
+                         cfg.counter);
+  } else if (cfg.unroll == 2) {
+    hipLaunchKernelGGL(propagate_mixed_kernel<2>, dim3(max_packs), dim3(kWave), 0, s, descs,
+                       n_prob, field, e, redo, accum, final_state, capacity);
+  } else {
+    hipLaunchKernelGGL(propagate_mixed_kernel<1>, dim3(max_packs), dim3(kWave), 0, s, descs,
+                       n_prob, field, e, redo, accum, final_state, capacity);
+  }
   return hipGetLastError();
 }
 

@@ -12,6 +12,11 @@ __global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint32_t v, uint64_t n
   if (i < n) p[i] = v;
 }
 
+__global__ void fill_f64_kernel(double* __restrict__ p, double v, uint64_t n) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 // ---------------------------------------------------------------- field
 // E(t) = -dA/dt of A(t) = -(E0/w) cos^2(pi t/tau) sin(w t + cep) for
 // |t| <= tau/2, zero outside (sin^2 pulse of Sec. II.D / III.A, centred at
@@ -268,6 +273,88 @@ __global__ void __launch_bounds__(kBlock) spectrum_kernel(const double* __restri
   }
 }
 
+// ------------------------------------------------------------ pack queue
+// Key of a pack: (n_len - 1) - remaining steps of its first (earliest-born)
+// lane, so that an ascending counting sort puts the longest packs first.
+__global__ void pack_keys_kernel(const Desc* __restrict__ descs, int n_prob, EnsPtrs e,
+                                 uint32_t max_packs, uint32_t n_len, uint32_t* __restrict__ keys,
+                                 uint32_t* __restrict__ hist) {
+  const uint32_t pack = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pack >= max_packs || pack >= e.pack_start[n_prob]) return;
+  int lo = 0, hi = n_prob;  // pack_start[lo] <= pack < pack_start[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (e.pack_start[mid] <= pack) lo = mid; else hi = mid;
+  }
+  const uint32_t first = e.order[e.live_start[lo] + (pack - e.pack_start[lo]) * kWave];
+  const uint32_t remaining = (uint32_t)(descs[lo].N - e.k0[first]);
+  const uint32_t key = (n_len - 1) - remaining;
+  keys[pack] = key;
+  atomicAdd(&hist[key], 1u);
+}
+
+__global__ void pack_scatter_kernel(const EnsPtrs e, int n_prob, uint32_t max_packs,
+                                    const uint32_t* __restrict__ keys,
+                                    uint32_t* __restrict__ cursor, uint32_t* __restrict__ queue) {
+  const uint32_t pack = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pack >= max_packs || pack >= e.pack_start[n_prob]) return;
+  queue[atomicAdd(&cursor[keys[pack]], 1u)] = pack;
+}
+
+// ---------------------------------------------------- batched dipole
+__global__ void dipole_batched_kernel(const Desc* __restrict__ descs,
+                                      const double* __restrict__ accum, double* __restrict__ v) {
+  const Desc& d = descs[blockIdx.y];
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > d.N) return;
+  const double sc = d.n_slots > 0 ? 2.0 / (double)d.n_slots : 0.0;
+  v[d.acc_off + k] = sc * accum[d.acc_off + k];
+}
+
+// -------------------------------------------------- batched spectrum
+// Problem blockIdx.y on its harmonic grid w_m = m h_step w, Hanning window
+// over |t| <= tau/2; one block per (m, problem), fixed-order reduction.
+__global__ void __launch_bounds__(kBlock) spectrum_batched_kernel(const Desc* __restrict__ descs,
+                                                                  const double* __restrict__ v,
+                                                                  double h_step, int n_omega,
+                                                                  double* __restrict__ V_re,
+                                                                  double* __restrict__ V_im,
+                                                                  double* __restrict__ yield) {
+  __shared__ double sr[kBlock], si[kBlock];
+  const Desc& d = descs[blockIdx.y];
+  const int m = blockIdx.x;
+  const double w = (double)m * h_step * d.omega;
+  const double tau_H = 0.5 * d.tau;
+  const double* vp = v + d.acc_off;
+  double ar = 0.0, ai = 0.0;
+  for (int k = threadIdx.x; k <= d.N; k += kBlock) {
+    const double t = d.t_first + (double)k * d.dt;
+    const double wh = fabs(t) <= tau_H ? 0.5 * (1.0 + cos(kPi * t / tau_H)) : 0.0;
+    double sn, cs;
+    sincos(w * t, &sn, &cs);
+    const double x = vp[k] * wh;
+    ar += x * cs;
+    ai += x * sn;
+  }
+  sr[threadIdx.x] = ar;
+  si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      sr[threadIdx.x] += sr[threadIdx.x + off];
+      si[threadIdx.x] += si[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double re = d.dt * sr[0], im = d.dt * si[0];
+    const size_t o = (size_t)blockIdx.y * n_omega + m;
+    V_re[o] = re;
+    V_im[o] = im;
+    yield[o] = w * w * (re * re + im * im);
+  }
+}
+
 inline unsigned blocks_for(uint64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -303,6 +390,12 @@ hipError_t launch_count(const Desc* descs, uint64_t n_slots, EnsPtrs e, const in
   return hipGetLastError();
 }
 
+hipError_t launch_fill_f64(double* p, double v, uint64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_f64_kernel, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_i32(int32_t* p, int32_t v, uint64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(fill_i32_kernel, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, p, v, n);
@@ -321,6 +414,39 @@ hipError_t launch_sort(const Desc* descs, int n_prob, uint64_t n_slots, uint64_t
                        descs, n_slots, cursor, e, select, out.order);
   hipLaunchKernelGGL(sort_bins_kernel, dim3(blocks_for(n_bins, kBlock)), dim3(kBlock), 0, s, hist,
                      n_bins, out.order);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_queue(const Desc* descs, int n_prob, EnsPtrs e, uint32_t max_packs,
+                             uint32_t n_len, uint32_t* keys, uint32_t* hist, uint32_t* cursor,
+                             uint32_t* queue, hipStream_t s) {
+  hipError_t err = launch_fill_u32(hist, 0u, (uint64_t)n_len + 1, s);
+  if (err != hipSuccess || max_packs == 0) return err;
+  hipLaunchKernelGGL(pack_keys_kernel, dim3(blocks_for(max_packs, kBlock)), dim3(kBlock), 0, s,
+                     descs, n_prob, e, max_packs, n_len, keys, hist);
+  hipLaunchKernelGGL(scan_bins_kernel, dim3(1), dim3(1024), 0, s, hist, (uint64_t)n_len);
+  hipLaunchKernelGGL(copy_u32_kernel, dim3(blocks_for((uint64_t)n_len + 1, kBlock)), dim3(kBlock),
+                     0, s, hist, cursor, (uint64_t)n_len + 1);
+  hipLaunchKernelGGL(pack_scatter_kernel, dim3(blocks_for(max_packs, kBlock)), dim3(kBlock), 0, s,
+                     e, n_prob, max_packs, keys, cursor, queue);
+  hipLaunchKernelGGL(sort_bins_kernel, dim3(blocks_for(n_len, kBlock)), dim3(kBlock), 0, s, hist,
+                     (uint64_t)n_len, queue);
+  return hipGetLastError();
+}
+
+hipError_t launch_dipole_batched(const Desc* descs, int n_prob, uint32_t n_kmax,
+                                 const double* accum, double* v, hipStream_t s) {
+  hipLaunchKernelGGL(dipole_batched_kernel, dim3(blocks_for(n_kmax, kBlock), n_prob), dim3(kBlock),
+                     0, s, descs, accum, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_spectrum_batched(const Desc* descs, int n_prob, const double* v, double h_step,
+                                   int n_omega, double* V_re, double* V_im, double* yield,
+                                   hipStream_t s) {
+  if (n_omega == 0) return hipSuccess;
+  hipLaunchKernelGGL(spectrum_batched_kernel, dim3(n_omega, n_prob), dim3(kBlock), 0, s, descs, v,
+                     h_step, n_omega, V_re, V_im, yield);
   return hipGetLastError();
 }
 

@@ -67,6 +67,10 @@ struct Layout {
   size_t bytes = 0;
   size_t off_descs = 0, off_slot = 0, off_field = 0, off_hist = 0, off_cursor = 0;
   size_t off_redo = 0, off_order2 = 0, off_runs2 = 0;
+  // plans only: pack queues
+  uint32_t max_packs = 0, n_len = 0;
+  size_t off_qkeys = 0, off_qhist = 0, off_qcursor = 0, off_queue = 0, off_queue2 = 0;
+  size_t off_counter = 0;
 };
 
 // Outputs of the counting sort into 64-lane packs.
@@ -94,18 +98,46 @@ hipError_t launch_sort(const Desc* descs, int n_prob, uint64_t n_slots, uint64_t
                        uint32_t* hist, uint32_t* cursor, EnsPtrs e, const int32_t* select,
                        PackOut out, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, uint64_t n, hipStream_t s);
+hipError_t launch_fill_f64(double* p, double v, uint64_t n, hipStream_t s);
 hipError_t launch_scale(const double* in, double* out, double scale, uint64_t n, hipStream_t s);
 hipError_t launch_spectrum(const double* v, int n_t, double t_first, double dt, double tau_H,
                            const double* omega, int n_omega, double* V_re, double* V_im,
                            double* yield, hipStream_t s);
 // propagate_f64.hip, propagate_mixed.hip
+// Launch form of the trajectory kernels: one wavefront per pack (grid =
+// max_packs), or a persistent grid pulling packs from queue[] through an
+// atomic counter (zeroed before the launch); U = unroll steps per loop trip.
+struct LaunchCfg {
+  int persistent = 0;
+  int unroll = 1;
+  uint32_t grid = 0;
+  const uint32_t* queue = nullptr;
+  uint32_t* counter = nullptr;
+};
+
 // dep_from (nullable, per slot): deposit amplitudes only from that step on.
 hipError_t launch_propagate_f64(const Desc* descs, int n_prob, const double* field, EnsPtrs e,
                                 const int32_t* dep_from, uint32_t max_packs, double* accum,
-                                double* final_state, uint64_t capacity, hipStream_t s);
+                                double* final_state, uint64_t capacity, hipStream_t s,
+                                const LaunchCfg& cfg);
 // redo (per slot, preset to -1): set to the first step left to the FP64 re-run.
 hipError_t launch_propagate_mixed(const Desc* descs, int n_prob, const double* field, EnsPtrs e,
                                   int32_t* redo, uint32_t max_packs, double* accum,
-                                  double* final_state, uint64_t capacity, hipStream_t s);
+                                  double* final_state, uint64_t capacity, hipStream_t s,
+                                  const LaunchCfg& cfg);
+// Pack queue ordered by remaining steps (longest first), ties by pack id:
+// queue[max_packs]; keys, hist, cursor: scratch of max_packs, n_len + 1, n_len + 1
+// entries with n_len = max_P N_P + 1.
+hipError_t launch_pack_queue(const Desc* descs, int n_prob, EnsPtrs e, uint32_t max_packs,
+                             uint32_t n_len, uint32_t* keys, uint32_t* hist, uint32_t* cursor,
+                             uint32_t* queue, hipStream_t s);
+// Batched dipole: v = (2 / n_slots_P) accum over every problem's segment.
+hipError_t launch_dipole_batched(const Desc* descs, int n_prob, uint32_t n_kmax,
+                                 const double* accum, double* v, hipStream_t s);
+// Batched spectrum on each problem's harmonic grid w_m = m h_step w_P,
+// m < n_omega; outputs [n_prob][n_omega].
+hipError_t launch_spectrum_batched(const Desc* descs, int n_prob, const double* v, double h_step,
+                                   int n_omega, double* V_re, double* V_im, double* yield,
+                                   hipStream_t s);
 
 }  // namespace sfhk

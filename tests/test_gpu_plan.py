@@ -1,0 +1,137 @@
+"""Plans: the batched whole path (one enqueue, persistent longest-first queue,
+batched dipole and spectra) and its HIP-graph replay, against the step-wise
+path and the oracle."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def sf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2608_13686_amd as sf
+    return sf
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    r = float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    print(f"relative L2 {r:.3e}")
+    return r
+
+
+def batch():
+    las = dict(workloads.N2_LASER, intensity_wcm2=2.2e14, cep=math.pi / 4)
+    probs = [workloads.h2_softcore(0.0),
+             workloads.n2(laser=las, align=workloads.cos2m(2)),
+             workloads.h2_softcore(align=workloads.cos2m(2),
+                                   laser=dict(workloads.H2_LASER, intensity_wcm2=1.5e14))]
+    return probs, [1500, 700, 900], [1001, 7, 8]
+
+
+def stepwise(sf, probs, n, seeds, h_max):
+    import torch
+    out = sf.run(probs, n, seeds, h_max=h_max)
+    torch.cuda.synchronize()
+    return [v.cpu().numpy() for v in out["v"]], [y.cpu().numpy() for y in out["yield"]]
+
+
+@pytest.mark.parametrize("tuning", [(0, 8, 1, 1), (1, 8, 1, 1), (1, 4, 2, 1)])
+def test_plan_equals_stepwise_path(sf, tuning):
+    import torch
+    probs, n, seeds = batch()
+    vs, ys = stepwise(sf, probs, n, seeds, 40.0)
+    plan = sf.Plan(probs, n, seeds, tuning=tuning, h_max=40.0)
+    plan.run()
+    torch.cuda.synchronize()
+    for i in range(len(probs)):
+        assert rel(plan.v_of(i).cpu().numpy(), vs[i]) < 1e-12
+        assert rel(plan.yield_[i].cpu().numpy(), ys[i]) < 1e-11
+    plan.close()
+
+
+def test_plan_batch_equals_problems_alone(sf):
+    import torch
+    probs, n, seeds = batch()
+    plan = sf.Plan(probs, n, seeds, tuning=(1, 8, 1, 1), h_max=30.0)
+    plan.run()
+    torch.cuda.synchronize()
+    for i in range(len(probs)):
+        one = sf.Plan([probs[i]], [n[i]], [seeds[i]], tuning=(1, 8, 1, 1), h_max=30.0)
+        one.run()
+        torch.cuda.synchronize()
+        assert rel(plan.v_of(i).cpu().numpy(), one.v.cpu().numpy()) < 1e-12
+        one.close()
+    plan.close()
+
+
+def test_plan_matches_oracle(sf, orc):
+    import torch
+    probs, n, seeds = batch()
+    plan = sf.Plan(probs, n, seeds, tuning=(1, 8, 1, 1), h_max=40.0)
+    plan.run()
+    torch.cuda.synchronize()
+    for i, (p, nn, sd) in enumerate(zip(probs, n, seeds)):
+        vo, _, _ = orc.dipole(p, sd, 0, nn, NTHREADS)
+        assert rel(plan.v_of(i).cpu().numpy(), vo) < 1e-10
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replays_match_eager_run(sf, precision):
+    """Three replays of the recorded graph, with eager work and host
+    synchronisation in between, each reproduce the eager run."""
+    import torch
+    probs, n, seeds = batch()
+    plan = sf.Plan(probs, n, seeds, precision=precision, tuning=(1, 8, 1, 1), h_max=40.0)
+    plan.run()
+    torch.cuda.synchronize()
+    v_ref = plan.v.cpu().numpy().copy()
+    y_ref = plan.yield_.cpu().numpy().copy()
+    side = torch.cuda.Stream()
+    plan.capture(side)
+    for r in range(3):
+        plan.v.zero_()
+        plan.yield_.fill_(-1.0)
+        junk = torch.randn(1 << 20, device="cuda").cumsum(0)  # unrelated eager work
+        torch.cuda.synchronize()
+        plan.replay(side)
+        side.synchronize()
+        assert rel(plan.v.cpu().numpy(), v_ref) < 1e-12, r
+        assert rel(plan.yield_.cpu().numpy(), y_ref) < 1e-11, r
+        del junk
+    plan.close()
+
+
+def test_plan_mixed_error_vs_fp64(sf):
+    import torch
+    probs, n, seeds = batch()
+    out = {}
+    for prec in ("fp64", "mixed"):
+        plan = sf.Plan(probs, n, seeds, precision=prec, tuning=(1, 8, 1, 1), h_max=40.0)
+        plan.run()
+        torch.cuda.synchronize()
+        out[prec] = [plan.v_of(i).cpu().numpy() for i in range(len(probs))]
+        plan.close()
+    for i in range(len(probs)):
+        assert rel(out["mixed"][i], out["fp64"][i]) < 5e-2
+
+
+def test_plan_rejects_bad_tuning(sf):
+    probs, n, seeds = batch()
+    for bad in [(2, 8, 1, 1), (1, 0 - 1, 1, 1), (1, 8, 3, 1), (1, 64, 1, 1)]:
+        with pytest.raises(sf.SfhkError):
+            sf.Plan(probs, n, seeds, tuning=bad)
+    with pytest.raises(sf.SfhkError) as ei:
+        sf.Plan(probs, n, seeds, tuning=(1, 8, 1, 2))
+    assert ei.value.status == 5
