@@ -3,11 +3,16 @@
 One step = the whole path over one batch: sample the ensemble, propagate
 every live trajectory (RK4 + monodromy + action + HK prefactor +
 recombination + dipole sum), normalise the dipole and take its harmonic
-spectrum.  Workload: N2 (Eq. 7, Table I, eps^2 = 0.5) at fixed alignment 0
-and 90 degrees, 1200 nm / 1.5e14 W/cm^2 / 4-cycle sin^2, dt = 0.05,
-1,048,576 trajectories per angle, FP64.
+spectrum.  Headline workload (``value``): N2 (Eq. 7, Table I, eps^2 = 0.5)
+at fixed alignment 0 and 90 degrees, 1200 nm / 1.5e14 W/cm^2 / 4-cycle
+sin^2, dt = 0.05, 1,048,576 trajectories per angle, plain FP64 kernel.
 
-Prints one JSON line (metric, value, roofline, cpu_baseline, ...).
+``variants`` in the same line: the mixed-precision form on the same
+trajectories (with its error against the FP64 run), and the batched
+H2 + N2 cos^4 workload over 64 lasers each (128 x 32,768 trajectories) as
+one tuned persistent plan replayed from a HIP graph.
+
+Prints one JSON line (metric, value, roofline, cpu_baseline, variants, ...).
 """
 import argparse
 import ctypes as C
@@ -90,6 +95,48 @@ def cpu_baseline(probs, seeds, budget_s=12.0):
                       f"({steps} live trajectory-steps, {el:.2f} s)"}
 
 
+def live_steps_of(sf, probs, n_traj, ens):
+    """Unit of work: sum over live trajectories of N - k0 (RK4 steps)."""
+    import torch
+    total, off = 0, 0
+    for p, n in zip(probs, n_traj):
+        N = sf.problem_steps(p)[0]
+        k0 = ens.k0[off:off + n].to(torch.int64)
+        w = ens.w[off:off + n]
+        total += int(((N - k0) * (w > 0)).sum().item())
+        off += n
+    return total
+
+
+def spectral_db(sf, prob, v_a, v_b, h_lo, h_hi):
+    """Median and 90th percentile of |10 log10(Y_a / Y_b)| over H[h_lo, h_hi]."""
+    import torch
+    N, t0, tau = sf.problem_steps(prob)
+    om = sf.harmonic_grid(prob, h_hi).cuda()
+    _, ya = sf.spectrum(v_a, t0, prob["dt"], tau / 2, om)
+    _, yb = sf.spectrum(v_b, t0, prob["dt"], tau / 2, om)
+    h = torch.arange(om.numel(), dtype=torch.float64) * 0.05
+    sel = (h >= h_lo) & (h <= h_hi)
+    db = (10 * torch.log10(ya.cpu() / yb.cpu())).abs()[sel].numpy()
+    return float(np.median(db)), float(np.percentile(db, 90))
+
+
+def timed_plan(sf, probs, n_traj, seeds, precision, tuning, steps, warmup, h_max):
+    import torch
+    plan = sf.Plan(probs, n_traj, seeds, precision=precision, tuning=tuning, h_max=h_max)
+    side = torch.cuda.Stream()
+    plan.capture(side)
+    for _ in range(max(warmup, 1)):
+        plan.replay(side)
+    side.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        plan.replay(side)
+    side.synchronize()
+    el = time.perf_counter() - t
+    return plan, el / steps
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +146,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (calibrates HBM counters)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="measure only the headline FP64 workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path shards by trajectory index with one "
@@ -203,6 +252,60 @@ def main():
                      "flops_per_traj_step": flop_step,
                      "flops_per_traj_step_with_recombination": [flops_per_step(p, True) for p in probs]},
     }
+    if not args.no_variants:
+        from paper_2608_13686_amd import autotune
+        variants = {}
+        # mixed precision on the same trajectories, error against the FP64 run
+        v64 = v.clone()
+        tun = autotune.cached(probs, "mixed") or (0, 8, 1, 1)
+        plan, sec = timed_plan(sf, probs, n_traj, seeds, "mixed", tun, args.steps, args.warmup,
+                               100.0)
+        errs = []
+        for i, (p, o, l) in enumerate(zip(probs, offs, lens)):
+            rel = float(torch.linalg.norm(plan.v_of(i) - v64[o:o + l]) /
+                        torch.linalg.norm(v64[o:o + l]))
+            med, p90 = spectral_db(sf, p, plan.v_of(i), v64[o:o + l], 15.0, 80.0)
+            errs.append({"theta_deg": round(math.degrees(p["align"]["theta"]), 3),
+                         "rel_l2_vs_fp64": rel, "spectral_db_median_H15_80": med,
+                         "spectral_db_p90_H15_80": p90})
+        plan.close()
+        del plan
+        # the same comparison with chaotic trajectories filtered by the prefactor
+        # cap |C| <= 1e3: the error of the FP32 stepping itself
+        capped = [dict(p, c_max=1e3) for p in probs]
+        errs_c = []
+        pf = sf.Plan(capped, n_traj, seeds, precision="fp64", tuning=tun, h_max=100.0)
+        pm = sf.Plan(capped, n_traj, seeds, precision="mixed", tuning=tun, h_max=100.0)
+        pf.run()
+        pm.run()
+        torch.cuda.synchronize()
+        for i, p in enumerate(capped):
+            rel = float(torch.linalg.norm(pm.v_of(i) - pf.v_of(i)) / torch.linalg.norm(pf.v_of(i)))
+            med, p90 = spectral_db(sf, p, pm.v_of(i), pf.v_of(i), 15.0, 80.0)
+            errs_c.append({"theta_deg": round(math.degrees(p["align"]["theta"]), 3),
+                           "rel_l2_vs_fp64": rel, "spectral_db_median_H15_80": med,
+                           "spectral_db_p90_H15_80": p90})
+        pf.close()
+        pm.close()
+        del pf, pm
+        variants["mixed"] = {"workload": wl["name"], "value": live_steps / sec,
+                             "unit": "trajectory-steps/s", "ms_per_step": sec * 1e3,
+                             "tuning": list(tun), "error_vs_fp64": errs,
+                             "error_vs_fp64_prefactor_cap_1e3": errs_c,
+                             "speedup_vs_fp64": (el / args.steps) / sec}
+        # batched cos^4 H2 + N2 over 64 lasers each, persistent plan, graph replay
+        wb = workloads.workload_batched(32768)
+        tun = autotune.cached(wb["problems"], wb["precision"]) or (1, 8, 1, 1)
+        plan, sec = timed_plan(sf, wb["problems"], wb["n_traj"], wb["seeds"], wb["precision"],
+                               tun, args.steps, args.warmup, 40.0)
+        ls = live_steps_of(sf, wb["problems"], wb["n_traj"], plan.ens)
+        variants["batched"] = {"workload": wb["name"], "value": ls / sec,
+                               "unit": "trajectory-steps/s", "ms_per_step": sec * 1e3,
+                               "live_trajectory_steps": ls, "precision": wb["precision"],
+                               "tuning": list(tun), "launch": "one HIP graph per step"}
+        plan.close()
+        del plan
+        out["variants"] = variants
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(probs, seeds)
     print(json.dumps(out), flush=True)

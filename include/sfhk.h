@@ -103,6 +103,9 @@ typedef struct {
   double sigma_perp; /* std. dev. of each transverse initial momentum       */
   int32_t n_steps;   /* 0: N = round(tau / dt); time grid t_k = -tau/2 + k dt */
   int32_t reserved;
+  double c_max;      /* optional prefactor cap: > 0 stops a trajectory's contributions from
+                        the first step with |C| > c_max (a filter of chaotic trajectories
+                        the paper does not use); <= 0: prefactor fully included */
 } sfhk_problem;
 
 /* Sampled ensemble: structure of arrays in device memory, `capacity` slots.

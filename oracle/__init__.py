@@ -31,6 +31,7 @@ class Problem(C.Structure):
         ("dt", C.c_double), ("gamma", C.c_double), ("w_cut", C.c_double),
         ("sigma_perp", C.c_double),
         ("n_steps", C.c_int32),
+        ("c_max", C.c_double),
     ]
 
 
@@ -57,7 +58,7 @@ def lib():
         L.orc_sample.argtypes = [P, C.c_uint64, C.c_uint64, C.c_uint64,
                                  C.POINTER(C.c_int32), dp, dp, dp, dp]
         L.orc_trajectory.argtypes = [P, C.c_int32, C.c_int32, dp, dp, dp, C.c_double,
-                                     dp, dp, dp]
+                                     dp, dp, dp, dp, dp]
         L.orc_trajectory.restype = C.c_int
         L.orc_run.argtypes = [P, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int32, dp,
                               C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
@@ -111,6 +112,7 @@ def make_problem(d):
     P.w_cut = d["w_cut"]
     P.sigma_perp = d["sigma_perp"]
     P.n_steps = int(d.get("n_steps", 0))
+    P.c_max = float(d.get("c_max", 0.0))
     return P
 
 
@@ -198,25 +200,28 @@ def sample(d, seed, first, n):
     return {"k0": k0, "q0": q0, "p0": p0, "nax": nax, "w": w}
 
 
-def trajectory(d, k0, q0, p0, nax, w=1.0, k_end=None, amplitudes=True):
-    """Propagate one trajectory; returns (a [N+1] complex or None, final [NFINAL])."""
+def trajectory(d, k0, q0, p0, nax, w=1.0, k_end=None, amplitudes=True, prefactors=False):
+    """Propagate one trajectory; returns (a [N+1] complex or None, final [NFINAL]),
+    plus C [N+1] complex when prefactors=True."""
     P = make_problem(d)
     N = n_steps(d)
     if k_end is None:
         k_end = N
     fin = np.zeros(NFINAL)
     q, p, n = _arr(q0, 3), _arr(p0, 3), _arr(nax, 3)
-    if amplitudes:
-        are = np.zeros(N + 1)
-        aim = np.zeros(N + 1)
-        rc = lib().orc_trajectory(C.byref(P), int(k0), int(k_end), _dp(q), _dp(p), _dp(n),
-                                  float(w), _dp(are), _dp(aim), _dp(fin))
-    else:
-        rc = lib().orc_trajectory(C.byref(P), int(k0), int(k_end), _dp(q), _dp(p), _dp(n),
-                                  float(w), None, None, _dp(fin))
+    are = np.zeros(N + 1) if amplitudes else None
+    aim = np.zeros(N + 1) if amplitudes else None
+    cre = np.zeros(N + 1) if prefactors else None
+    cim = np.zeros(N + 1) if prefactors else None
+    ptr = lambda a: _dp(a) if a is not None else None
+    rc = lib().orc_trajectory(C.byref(P), int(k0), int(k_end), _dp(q), _dp(p), _dp(n), float(w),
+                              ptr(are), ptr(aim), ptr(cre), ptr(cim), _dp(fin))
     if rc != 0:
         raise ValueError("orc_trajectory rejected its arguments")
-    return ((are + 1j * aim) if amplitudes else None), fin
+    a = (are + 1j * aim) if amplitudes else None
+    if prefactors:
+        return a, fin, cre + 1j * cim
+    return a, fin
 
 
 def run(d, seed, first, n, nthreads=None):

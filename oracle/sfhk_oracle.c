@@ -334,10 +334,14 @@ static void rk4_step(const orc_problem* P, const double n[3], int32_t k, double 
  * Eq. (1) for psi_c).  Readings: the phase is Phi = S_-> + Re S_down^0 - Ip t
  * with Re S_down^0 = Ip t0 at first order, plus p0.q0 from Eq. (1); the
  * square root of det R is continued along the trajectory (C_{k0} = 1, each
- * step takes the root closer to the previous C). */
+ * step takes the root closer to the previous C).  Optional prefactor cap
+ * (not in the paper, whose prefactor is fully included; off when c_max <= 0):
+ * from the first step with |C_k| > c_max on, the trajectory contributes
+ * nothing and is not propagated further. */
 static int traj_core(const orc_problem* P, int32_t k0, int32_t k_end, const double q0[3],
                      const double p0[3], const double n[3], double w, double* amp_re,
-                     double* amp_im, double* accum, double* final_state) {
+                     double* amp_im, double* c_re, double* c_im, double* accum,
+                     double* final_state) {
   int32_t N;
   orc_laser(P, NULL, NULL, NULL, &N);
   if (k0 < 0 || k_end < k0 || k_end > N) return -1;
@@ -358,6 +362,9 @@ static int traj_core(const orc_problem* P, int32_t k0, int32_t k_end, const doub
     if (fabs(carg(D / Dprev)) > 0.5 * ORC_PI) flips += 1.0;
     C = c;
     Dprev = D;
+    if (c_re) c_re[k] = creal(C);
+    if (c_im) c_im[k] = cimag(C);
+    if (P->c_max > 0.0 && cabs(C) > P->c_max) break;
     double phi = y[42] - P->Ip * (orc_time(P, k) - t0) + p0q0;
     double rre, rim;
     orc_recombination(P, n, y + 3, y, &rre, &rim);
@@ -379,8 +386,8 @@ static int traj_core(const orc_problem* P, int32_t k0, int32_t k_end, const doub
 
 int orc_trajectory(const orc_problem* P, int32_t k0, int32_t k_end, const double q0[3],
                    const double p0[3], const double nax[3], double w, double* amp_re,
-                   double* amp_im, double* final_state) {
-  return traj_core(P, k0, k_end, q0, p0, nax, w, amp_re, amp_im, NULL, final_state);
+                   double* amp_im, double* c_re, double* c_im, double* final_state) {
+  return traj_core(P, k0, k_end, q0, p0, nax, w, amp_re, amp_im, c_re, c_im, NULL, final_state);
 }
 
 /* ------------------------------------------------------------ the ensemble */
@@ -406,7 +413,7 @@ static void* run_range(void* arg) {
     double q0[3], p0[3], nax[3], w;
     sample_one(J->P, J->seed, J->first + i, N, E0, &k0, q0, p0, nax, &w);
     if (w == 0.0) continue;
-    traj_core(J->P, k0, N, q0, p0, nax, w, NULL, NULL, J->accum, NULL);
+    traj_core(J->P, k0, N, q0, p0, nax, w, NULL, NULL, NULL, NULL, J->accum, NULL);
     J->live_steps += (uint64_t)(N - k0);
     J->n_live += 1;
   }

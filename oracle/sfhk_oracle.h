@@ -53,6 +53,7 @@ typedef struct {
   /* time step, coherent-state width, weight cut, transverse momentum sigma */
   double dt, gamma, w_cut, sigma_perp;
   int32_t n_steps; /* 0 = round(tau / dt) */
+  double c_max;    /* > 0: a trajectory stops contributing once |C| > c_max */
 } orc_problem;
 
 /* laser constants: omega, peak field E0, pulse length tau, steps N */
@@ -75,11 +76,12 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 void orc_sample(const orc_problem* P, uint64_t seed, uint64_t first, uint64_t n, int32_t* k0,
                 double* q0, double* p0, double* nax, double* w);
 /* propagate one trajectory from step k0 to step k_end (<= N).  amp_re/amp_im
- * (nullable, length N+1) receive a_k for k0 <= k <= k_end; final (nullable)
- * receives ORC_NFINAL doubles at k_end.  Returns 0, or -1 on bad input. */
+ * (nullable, length N+1) receive a_k for k0 <= k <= k_end; c_re/c_im
+ * (nullable, length N+1) the HK prefactor C_k; final (nullable) receives
+ * ORC_NFINAL doubles at the last step reached.  Returns 0, or -1 on bad input. */
 int orc_trajectory(const orc_problem* P, int32_t k0, int32_t k_end, const double q0[3],
                    const double p0[3], const double nax[3], double w, double* amp_re,
-                   double* amp_im, double* final_state);
+                   double* amp_im, double* c_re, double* c_im, double* final_state);
 /* whole estimator: sample trajectories first..first+n-1, propagate the live
  * ones, accum[k] = sum_j Re a_jk (length N+1).  Returns 0 or -1. */
 int orc_run(const orc_problem* P, uint64_t seed, uint64_t first, uint64_t n, int32_t nthreads,

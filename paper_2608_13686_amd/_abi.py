@@ -45,7 +45,7 @@ class Align(C.Structure):
 class Problem(C.Structure):
     _fields_ = [("tgt", Target), ("las", Laser), ("al", Align), ("dt", C.c_double),
                 ("gamma_cs", C.c_double), ("w_cut", C.c_double), ("sigma_perp", C.c_double),
-                ("n_steps", C.c_int32), ("reserved", C.c_int32)]
+                ("n_steps", C.c_int32), ("reserved", C.c_int32), ("c_max", C.c_double)]
 
 
 class Ensemble(C.Structure):
@@ -147,6 +147,7 @@ def make_problems(dicts):
         P.w_cut = d["w_cut"]
         P.sigma_perp = d["sigma_perp"]
         P.n_steps = int(d.get("n_steps", 0))
+        P.c_max = float(d.get("c_max", 0.0))
     arr._keep = keep
     return arr
 

@@ -68,6 +68,7 @@ sfhk_status check_problem(const sfhk_problem* p, int idx) {
     return fail(SFHK_E_INVALID, "problem %d: w_cut must be >= 0", idx);
   if (!(is_finite(p->sigma_perp) && p->sigma_perp >= 0))
     return fail(SFHK_E_INVALID, "problem %d: sigma_perp must be >= 0", idx);
+  if (!is_finite(p->c_max)) return fail(SFHK_E_INVALID, "problem %d: c_max not finite", idx);
   if (p->n_steps < 0) return fail(SFHK_E_INVALID, "problem %d: n_steps must be >= 0", idx);
   const sfhk_target& T = p->tgt;
   if (!(is_finite(T.R) && T.R >= 0)) return fail(SFHK_E_INVALID, "problem %d: R must be >= 0", idx);
@@ -154,6 +155,7 @@ Desc make_desc(const sfhk_problem& p) {
   d.wpow = 0.5 * (2.0 / d.kappa - 1.0);
   d.kcube3 = d.kappa * d.kappa * d.kappa / 3.0;
   d.inv_E0 = E0 > 0 ? 1.0 / E0 : 0.0;
+  d.c_max2 = p.c_max > 0.0 ? p.c_max * p.c_max : 0.0;
   d.nfix[0] = std::sin(p.al.theta) * std::cos(p.al.phi);
   d.nfix[1] = std::sin(p.al.theta) * std::sin(p.al.phi);
   d.nfix[2] = std::cos(p.al.theta);

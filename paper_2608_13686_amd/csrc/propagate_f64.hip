@@ -61,17 +61,23 @@ __device__ __forceinline__ void run_pack(const Desc* __restrict__ descs,
   const int kmin = __builtin_amdgcn_readfirstlane(k0);
   double acc_reg = 0.0;
 
+  int kend = N + 1;  // first step without contribution (prefactor cap)
+
   for (int kc = kmin; kc <= N; kc += U) {
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int k = kc + u;
     if (k > N) break;
-    const bool live = k >= k0;
+    bool live = k >= k0 && k < kend;
     double re_a = 0.0;
     if (live) {
       prefactor_step(Rr, Ri, Cre, Cim, flips);
-      if (k >= kdep)
+      if (d.c_max2 > 0.0 && Cre * Cre + Cim * Cim > d.c_max2) {
+        kend = k;
+        live = false;
+      } else if (k >= kdep) {
         re_a = amplitude_re(d, n, p, q, Cre, Cim, S, d.t_first + (double)k * h, t0, p0q0, w);
+      }
     }
     deposit(re_a, k, N, lane, acc_reg, acc);
     if (k >= N || !live) continue;

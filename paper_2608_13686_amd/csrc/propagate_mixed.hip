@@ -52,14 +52,15 @@ __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
   double* __restrict__ acc = accum + d.acc_off;
   const int kmin = __builtin_amdgcn_readfirstlane(k0);
   double acc_reg = 0.0;
-  int kend = N + 1;  // first step left to the FP64 re-run (N + 1: none)
+  int kend = N + 1;  // first step not run here (FP64 re-run or prefactor cap)
+  int kcap = N + 1;  // step at which the prefactor cap stopped the trajectory
 
   for (int kc = kmin; kc <= N; kc += U) {
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int k = kc + u;
     if (k > N) break;
-    const bool live = k >= k0 && k < kend;
+    bool live = k >= k0 && k < kend;
     double re_a = 0.0;
     if (live) {
       // HK matrix and its determinant from the FP32 monodromy matrix, in FP32;
@@ -76,9 +77,16 @@ __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
       float Dr, Di;
       det3c(Rr, Ri, Dr, Di);
       sqrt_continued((double)Dr, (double)Di, Cre, Cim, flips);
-      const double pd_[3] = {(double)p[0], (double)p[1], (double)p[2]};
-      const double qd_[3] = {(double)q[0], (double)q[1], (double)q[2]};
-      re_a = amplitude_re(d, n, pd_, qd_, Cre, Cim, S, d.t_first + (double)k * hd, t0, p0q0, w);
+      if (d.c_max2 > 0.0 && Cre * Cre + Cim * Cim > d.c_max2) {
+        kend = k;  // prefactor cap: no contribution from here on
+        kcap = k;
+        live = false;
+      } else {
+        const double pd_[3] = {(double)p[0], (double)p[1], (double)p[2]};
+        const double qd_[3] = {(double)q[0], (double)q[1], (double)q[2]};
+        re_a = amplitude_re(d, n, pd_, qd_, Cre, Cim, S, d.t_first + (double)k * hd, t0, p0q0,
+                            w);
+      }
     }
     deposit(re_a, k, N, lane, acc_reg, acc);
     if (k >= N || !live) continue;
@@ -195,7 +203,8 @@ __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
   }
   }
 
-  if (final_state != nullptr && valid && kend > N) {
+  // trajectories handed to the FP64 re-run get their final state from it
+  if (final_state != nullptr && valid && (kend > N || kcap <= N)) {
     double* f = final_state + slot;
     const uint64_t st = capacity;
 #pragma unroll

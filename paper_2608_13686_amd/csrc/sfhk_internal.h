@@ -37,6 +37,7 @@ struct Desc {
   double g_norm[SFHK_MAX_GTO], g_i2a[SFHK_MAX_GTO];
   int32_t g_l[SFHK_MAX_GTO];
   double g_inv4k_min;  // smallest 1/(4 kappa2) over the primitives
+  double c_max2;       // prefactor cap squared (0: none)
 };
 
 // Device pointers of the ensemble, passed by value to kernels.

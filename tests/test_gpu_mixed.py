@@ -112,3 +112,20 @@ def test_mixed_hands_chaotic_trajectories_to_fp64(sf):
     rel = np.max(np.abs(fmx[0:6, regular] - f64[0:6, regular]) / np.maximum(1, np.abs(f64[0:6, regular])))
     print(f"regular trajectories: max relative (q, p) difference {rel:.3e}")
     assert rel < 1e-3
+
+
+def test_mixed_error_with_prefactor_cap(sf):
+    """With chaotic trajectories filtered by a prefactor cap (|C| <= 1e3), the
+    dipole is carried by regular trajectories and the mixed form's error is
+    the FP32 stepping error itself; stated here, bounded by 1e-3."""
+    probs = [dict(workloads.n2(0.0), c_max=1e3), dict(workloads.n2(90.0), c_max=1e3),
+             dict(workloads.h2_softcore(), c_max=1e3)]
+    n, seeds = [65536, 65536, 65536], [1002, 1002, 1001]
+    ens, out = both_precisions(sf, probs, n, seeds)
+    offs, lens = sf.accum_layout(probs)
+    for p, o, l in zip(probs, offs, lens):
+        v64 = out["fp64"][0][o:o + l]
+        vmx = out["mixed"][0][o:o + l]
+        rel = np.linalg.norm(vmx - v64) / np.linalg.norm(v64)
+        print(f"capped {p['name']} theta={p['align']['theta']:.3f}: mixed vs FP64 relative L2 {rel:.3e}")
+        assert rel < 1e-3

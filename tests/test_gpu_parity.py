@@ -301,3 +301,15 @@ def test_full_size_n2_sampled_trajectories_and_linearity(sf, orc):
         sf.propagate(probs, e, accum=acc2, workspace=w)
     torch.cuda.synchronize()
     assert rel_l2(acc2.cpu().numpy(), acc_full) < 1e-11
+
+
+@pytest.mark.parametrize("precision", ["fp64"])
+def test_prefactor_cap_matches_oracle(sf, orc, precision):
+    """The optional prefactor cap: contributions stop at the first step with
+    |C| > c_max, on the GPU as in the oracle."""
+    probs = [dict(workloads.n2(0.0), c_max=1e3), dict(workloads.h2_softcore(), c_max=100.0)]
+    n, seeds = [3000, 4096], [1002, 1001]
+    vg, _ = gpu_dipole(sf, probs, n, seeds)
+    for p, v, nn, sd in zip(probs, vg, n, seeds):
+        vo, _, _ = orc.dipole(p, sd, 0, nn, NTHREADS)
+        assert rel_l2(v, vo) < REL_L2

@@ -586,3 +586,26 @@ def test_tunnel_exit_and_weight_against_exact_saddle_point(orc):
         errs[lam] = (max(e_exp), max(e_q))
     assert errs[12000.0][0] < 0.005 and errs[12000.0][1] < 0.01, errs
     assert errs[4000.0][0] / errs[12000.0][0] > 5 and errs[4000.0][1] / errs[12000.0][1] > 5, errs
+
+
+def test_prefactor_cap_truncates_contributions(orc):
+    """With a prefactor cap, a trajectory's amplitudes are the uncapped ones up
+    to the first step with |C_k| > c_max and zero from there on; a cap above
+    every |C_k| changes nothing."""
+    p = workloads.n2(0.0)
+    ics = _live_ics(orc, p, 1002, 12)
+    hit = 0
+    for (k0, q0, p0, n, w) in ics:
+        a, _, c = orc.trajectory(p, k0, q0, p0, n, w, prefactors=True)
+        cmax = 30.0
+        capped = dict(p, c_max=cmax)
+        ac, _ = orc.trajectory(capped, k0, q0, p0, n, w)
+        over = np.nonzero(np.abs(c[k0:]) > cmax)[0]
+        kc = k0 + over[0] if over.size else len(a)
+        hit += over.size > 0
+        assert np.array_equal(ac[:kc], a[:kc])
+        assert np.all(ac[kc:] == 0)
+        big = dict(p, c_max=10 * np.abs(c).max() + 1)
+        ab, _ = orc.trajectory(big, k0, q0, p0, n, w)
+        assert np.array_equal(ab, a)
+    assert hit > 0

@@ -14,7 +14,8 @@ Problem dictionaries have the layout::
      "target": {"R", "Ip" (hartree), "centers": [2 x {"Zinf","dZ","alpha","eps2"}],
                 "gto": [(center, l, a, c), ...]},
      "align":  {"kind": "fixed"|"cos2m", "theta", "phi", "m"},
-     "dt", "gamma", "w_cut", "sigma_perp", "n_steps" (0 = round(tau/dt))}
+     "dt", "gamma", "w_cut", "sigma_perp", "n_steps" (0 = round(tau/dt)),
+     optional "c_max" (> 0: prefactor cap; absent = prefactor fully included)}
 
 Atomic units throughout, except the laser (nm, W/cm^2, cycles, rad).
 """
