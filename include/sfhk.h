@@ -259,6 +259,60 @@ sfhk_status sfhk_plan_replay(sfhk_plan* plan, void* stream);
 /* Release the plan and its graph (host resources only). */
 void sfhk_plan_destroy(sfhk_plan* plan);
 
+/* ---------------------------------------------------------------- serving
+ * Time-sliced propagation for continuous batching of spectrum requests.  A
+ * request (one problem, its trajectory count and seed) owns a contiguous
+ * device buffer (its share of the caller's serving pool) and one slot of a
+ * device request table.  sfhk_serve_window advances any set of admitted
+ * requests by a window of RK4 steps in one launch; the trajectory state stays
+ * on the device between windows, so requests can be admitted and retired
+ * between any two windows while others are in flight.  A request whose
+ * windows have covered steps 0..N is finalised (dipole and spectrum).
+ * Ownership: the caller owns the pool, the table and every request buffer;
+ * the library keeps no pointer between calls except those it writes into the
+ * device table.  Calls enqueue on `stream` and return at once; a buffer or
+ * slot may be reused once the work that used it has completed on the stream.
+ * Errors: a bad argument returns SFHK_E_INVALID, a buffer below the request's
+ * footprint SFHK_E_NOMEM, a window of more than 2^32 work-items
+ * SFHK_E_UNSUPPORTED, all before anything is enqueued; a launch failure
+ * returns SFHK_E_DEVICE. */
+
+/* Host only.  Device bytes of one request's buffer (its admission footprint). */
+size_t sfhk_request_bytes(const sfhk_problem* p, uint64_t n_traj, int32_t n_omega);
+
+/* Host only.  Byte offsets, inside the request buffer, of its results:
+ * v [N+1], V_re [n_omega], V_im [n_omega], yield [n_omega] (all double). */
+sfhk_status sfhk_request_layout(const sfhk_problem* p, uint64_t n_traj, int32_t n_omega,
+                                size_t offsets[4]);
+
+/* Host only.  Bytes of a device request table with max_requests slots. */
+size_t sfhk_request_table_bytes(int32_t max_requests);
+
+/* Admit a request into slot `slot` (< table_slots) of the device request table
+ * `table` (sfhk_request_table_bytes(table_slots) bytes): lay out its buffers in `buffer`
+ * (device, >= sfhk_request_bytes), and enqueue its field table, the sampling
+ * of trajectories first_index .. first_index + n_traj - 1 under `seed`
+ * (as sfhk_sample_initial), their packing and the zeroing of its dipole
+ * accumulator.  Spectrum grid: w_m = m h_step w_laser, m < n_omega. */
+sfhk_status sfhk_request_init(const sfhk_problem* p, uint64_t n_traj, uint64_t seed,
+                              uint64_t first_index, double h_step, int32_t n_omega,
+                              void* buffer, size_t buffer_bytes, void* table, int32_t table_slots,
+                              int32_t slot, void* stream);
+
+/* Advance n admitted requests by one window each: request slots[i] over its
+ * steps [k_from[i], k_to[i]) (windows of one request must be launched in
+ * order and without gaps, starting at 0); n_traj[i] is its trajectory count
+ * (a larger value only launches idle wavefronts, a smaller one drops packs).
+ * The same physics as sfhk_propagate in FP64 (Sec. II.A; Eq. 4-6). */
+sfhk_status sfhk_serve_window(void* table, int32_t table_slots, int32_t n, const int32_t* slots,
+                              const uint64_t* n_traj, const int32_t* k_from, const int32_t* k_to,
+                              void* stream);
+
+/* Dipole (v = 2 accum / n_traj) and spectrum of a request whose windows have
+ * covered steps 0..N; results at sfhk_request_layout's offsets. */
+sfhk_status sfhk_request_finalize(const sfhk_problem* p, int32_t n_omega, void* table,
+                                  int32_t table_slots, int32_t slot, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

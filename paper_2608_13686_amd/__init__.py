@@ -166,7 +166,8 @@ def harmonic_grid(prob, h_max, h_step=0.05):
     return torch.arange(n, dtype=torch.float64) * h_step * omega0
 
 
-def run(probs, n_traj, seeds, precision="fp64", h_max=40.0, device="cuda", stream=None):
+def run(probs, n_traj, seeds, precision="fp64", h_max=40.0, h_step=0.05, device="cuda",
+        stream=None):
     """Whole path for a list of problems: sample, propagate, dipole and the
     spectrum of each problem on its harmonic grid.  Returns a dict."""
     ens, ws = sample_initial(probs, n_traj, seeds, device=device, stream=stream)
@@ -176,7 +177,7 @@ def run(probs, n_traj, seeds, precision="fp64", h_max=40.0, device="cuda", strea
     out = {"v": [], "V": [], "yield": [], "omega": [], "t_first": [], "ensemble": ens}
     for p, o, n in zip(probs, offs, lens):
         N, t0, tau = problem_steps(p)
-        om = harmonic_grid(p, h_max).to(device)
+        om = harmonic_grid(p, h_max, h_step).to(device)
         V, Y = spectrum(v[o:o + n], t0, p["dt"], 0.5 * tau, om, stream=stream)
         out["v"].append(v[o:o + n])
         out["V"].append(V)

@@ -15,7 +15,9 @@ STATUS = {0: "SFHK_OK", 1: "SFHK_E_INVALID", 2: "SFHK_E_NOMEM", 3: "SFHK_E_DEVIC
 EXPORTS = ["sfhk_abi_version", "sfhk_last_error", "sfhk_problem_steps", "sfhk_workspace_bytes",
            "sfhk_sample_initial", "sfhk_propagate", "sfhk_dipole", "sfhk_spectrum",
            "sfhk_plan_workspace_bytes", "sfhk_plan_create", "sfhk_plan_run", "sfhk_plan_capture",
-           "sfhk_plan_replay", "sfhk_plan_destroy"]
+           "sfhk_plan_replay", "sfhk_plan_destroy", "sfhk_request_bytes", "sfhk_request_layout",
+           "sfhk_request_table_bytes", "sfhk_request_init", "sfhk_serve_window",
+           "sfhk_request_finalize"]
 
 
 class Center(C.Structure):
@@ -108,6 +110,23 @@ def lib():
             getattr(L, f).restype = C.c_int
         L.sfhk_plan_destroy.argtypes = [C.c_void_p]
         L.sfhk_plan_destroy.restype = None
+        L.sfhk_request_bytes.argtypes = [P, C.c_uint64, C.c_int32]
+        L.sfhk_request_bytes.restype = C.c_size_t
+        L.sfhk_request_layout.argtypes = [P, C.c_uint64, C.c_int32, C.POINTER(C.c_size_t)]
+        L.sfhk_request_layout.restype = C.c_int
+        L.sfhk_request_table_bytes.argtypes = [C.c_int32]
+        L.sfhk_request_table_bytes.restype = C.c_size_t
+        L.sfhk_request_init.argtypes = [P, C.c_uint64, C.c_uint64, C.c_uint64, C.c_double,
+                                        C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                                        C.c_int32, C.c_int32, C.c_void_p]
+        L.sfhk_request_init.restype = C.c_int
+        i32p = C.POINTER(C.c_int32)
+        L.sfhk_serve_window.argtypes = [C.c_void_p, C.c_int32, C.c_int32, i32p, u64p, i32p,
+                                        i32p, C.c_void_p]
+        L.sfhk_serve_window.restype = C.c_int
+        L.sfhk_request_finalize.argtypes = [P, C.c_int32, C.c_void_p, C.c_int32, C.c_int32,
+                                            C.c_void_p]
+        L.sfhk_request_finalize.restype = C.c_int
         _lib = L
     return _lib
 

@@ -305,6 +305,15 @@ sfhk_status stage_problems(const std::vector<Desc>& descs, const Workspace& ws,
 
 }  // namespace
 
+// entry points of this file used by the serving ABI (serve_abi.hip)
+namespace sfhk_abi_detail {
+sfhk_status check_problem_ext(const sfhk_problem* p, int idx) { return check_problem(p, idx); }
+Desc make_desc_ext(const sfhk_problem& p) { return make_desc(p); }
+sfhk_status fail_ext(sfhk_status st, const char* msg) { return fail(st, "%s", msg); }
+sfhk_status hip_fail_ext(hipError_t e, const char* where) { return hip_fail(e, where); }
+sfhk_status ok_ext() { return ok(); }
+}  // namespace sfhk_abi_detail
+
 extern "C" {
 
 int32_t sfhk_abi_version(void) { return SFHK_ABI_VERSION; }

@@ -1,0 +1,421 @@
+"""Continuous-batching server of HHG-spectrum requests.
+
+Requests (one problem, a trajectory count and a seed each) are admitted by
+their device-memory footprint into a caller-sized pool and a slot of the
+device request table; every scheduling step launches one window of RK4
+steps over all admitted requests (``sfhk_serve_window``), so that requests
+arriving while others run join at the next window and their work overlaps on
+the device.  A request whose windows cover its whole pulse is finalised
+(dipole + spectrum), its result copied out and its memory released.
+
+The scheduling logic runs against an executor: ``HipExecutor`` drives the
+HIP library; the tests drive the same scheduler with a host-only executor.
+"""
+import ctypes as C
+import math
+import time
+from collections import deque
+
+from . import _abi
+
+ALIGN = 256
+
+
+class PoolAllocator:
+    """First-fit allocator of byte ranges in [0, size) with 256-byte
+    alignment; freed ranges are coalesced with their neighbours."""
+
+    def __init__(self, size, align=ALIGN):
+        self.size = int(size)
+        self.align = align
+        self.free_list = [(0, self.size)]  # sorted (offset, length)
+        self.used = {}
+
+    def _round(self, n):
+        return (int(n) + self.align - 1) // self.align * self.align
+
+    def alloc(self, nbytes):
+        n = self._round(max(nbytes, 1))
+        for i, (off, ln) in enumerate(self.free_list):
+            if ln >= n:
+                if ln == n:
+                    self.free_list.pop(i)
+                else:
+                    self.free_list[i] = (off + n, ln - n)
+                self.used[off] = n
+                return off
+        return None
+
+    def free(self, off):
+        n = self.used.pop(off)
+        fl = self.free_list
+        fl.append((off, n))
+        fl.sort()
+        merged = []
+        for o, ln in fl:
+            if merged and merged[-1][0] + merged[-1][1] == o:
+                merged[-1] = (merged[-1][0], merged[-1][1] + ln)
+            else:
+                merged.append((o, ln))
+        self.free_list = merged
+
+    @property
+    def bytes_used(self):
+        return sum(self.used.values())
+
+    def largest_free(self):
+        return max((ln for _, ln in self.free_list), default=0)
+
+
+class Request:
+    def __init__(self, tag, problem, n_traj, seed, arrival, deadline=None):
+        self.tag = tag
+        self.deadline = deadline
+        self.error = None
+        self.problem = problem
+        self.n_traj = int(n_traj)
+        self.seed = int(seed)
+        self.arrival = arrival
+        self.admitted = None
+        self.finished = None
+        self.slot = None
+        self.offset = None
+        self.bytes = None
+        self.n_steps = None
+        self.k_next = 0
+        self.handle = None
+        self.event = None
+        self.result = None
+        self.state = "waiting"
+
+
+class HipExecutor:
+    """Device side of the server: a torch uint8 pool, the request table and
+    the C ABI calls, all on one torch stream."""
+
+    def __init__(self, pool_bytes, max_requests, n_omega, h_step, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=device)
+        nb = _abi.lib().sfhk_request_table_bytes(max_requests)
+        self.table = torch.empty(nb, dtype=torch.uint8, device=device)
+        self.max_requests = max_requests
+        self.n_omega = n_omega
+        self.h_step = h_step
+        self.stream = stream or torch.cuda.current_stream()
+        self._h = C.c_void_p(self.stream.cuda_stream)
+
+    def footprint(self, problem, n_traj):
+        arr = _abi.make_problems([problem])
+        nb = _abi.lib().sfhk_request_bytes(arr, int(n_traj), self.n_omega)
+        if nb == 0:
+            raise _abi.SfhkError(1, "sfhk_request_bytes")
+        return nb
+
+    def steps(self, problem):
+        from . import problem_steps
+        return problem_steps(problem)[0]
+
+    def init(self, req):
+        req.handle = arr = _abi.make_problems([req.problem])
+        _abi.check(_abi.lib().sfhk_request_init(
+            arr, req.n_traj, req.seed, 0, float(self.h_step), self.n_omega,
+            C.c_void_p(self.pool.data_ptr() + req.offset), req.bytes,
+            C.c_void_p(self.table.data_ptr()), self.max_requests, req.slot, self._h),
+            "sfhk_request_init")
+
+    def window(self, entries):
+        """entries: list of (request, k_from, k_to)."""
+        n = len(entries)
+        slots = (C.c_int32 * n)(*[r.slot for r, _, _ in entries])
+        ntraj = (C.c_uint64 * n)(*[r.n_traj for r, _, _ in entries])
+        kf = (C.c_int32 * n)(*[a for _, a, _ in entries])
+        kt = (C.c_int32 * n)(*[b for _, _, b in entries])
+        _abi.check(_abi.lib().sfhk_serve_window(C.c_void_p(self.table.data_ptr()),
+                                                self.max_requests, n, slots, ntraj, kf, kt,
+                                                self._h), "sfhk_serve_window")
+        ev = self.torch.cuda.Event()
+        ev.record(self.stream)
+        return ev
+
+    def finalize(self, req):
+        _abi.check(_abi.lib().sfhk_request_finalize(
+            req.handle, self.n_omega, C.c_void_p(self.table.data_ptr()),
+            self.max_requests, req.slot, self._h), "sfhk_request_finalize")
+        ev = self.torch.cuda.Event()
+        ev.record(self.stream)
+        return ev
+
+    def done(self, ev):
+        return ev.query()
+
+    def wait(self, ev):
+        ev.synchronize()
+
+    def result(self, req):
+        torch = self.torch
+        offs = (C.c_size_t * 4)()
+        _abi.check(_abi.lib().sfhk_request_layout(req.handle, req.n_traj, self.n_omega, offs),
+                   "sfhk_request_layout")
+        base = req.offset
+        N = req.n_steps
+
+        def f64(off, n):
+            return self.pool[base + off: base + off + 8 * n].view(torch.float64).cpu()
+
+        out = {"v": f64(offs[0], N + 1), "V_re": f64(offs[1], self.n_omega),
+               "V_im": f64(offs[2], self.n_omega), "yield": f64(offs[3], self.n_omega)}
+        return out
+
+
+class Server:
+    """Admission by footprint and table slots; every scheduling step launches
+    one window of `window` RK4 steps for the requests it picks, with at most
+    `in_flight` launches queued on the device.
+
+    Policies: ``"ps"`` advances every admitted request each step (processor
+    sharing); ``"srpt"`` advances the requests with the least remaining work
+    (trajectories x steps left) first, adding requests until the launch holds
+    at least `fill_waves` wavefronts, so the device stays full while short
+    requests overtake long ones."""
+
+    def __init__(self, executor, pool_bytes, max_requests=64, window=1024, in_flight=2,
+                 policy="ps", fill_waves=16384, clock=time.perf_counter):
+        if policy not in ("ps", "srpt"):
+            raise ValueError("policy must be 'ps' or 'srpt'")
+        if window < 1 or in_flight < 1 or max_requests < 1:
+            raise ValueError("window, in_flight and max_requests must be positive")
+        self.x = executor
+        self.alloc = PoolAllocator(pool_bytes)
+        self.free_slots = deque(range(max_requests))
+        self.window = int(window)
+        self.in_flight = in_flight
+        self.policy = policy
+        self.fill_waves = int(fill_waves)
+        self.clock = clock
+        self.failed = []
+        self.timed_out = []
+        self.cancelled = []
+        self.peak_bytes = 0
+        self.peak_active = 0
+        self.waiting = deque()
+        self.active = []
+        self.finishing = []
+        self.completed = []
+        self.rejected = []
+        self._events = deque()
+
+    # ------------------------------------------------------------ requests
+    def submit(self, tag, problem, n_traj, seed, arrival=None, timeout=None):
+        """Queue a request; `timeout` (seconds after arrival) drops it if it
+        has not finished by then."""
+        arrival = self.clock() if arrival is None else arrival
+        req = Request(tag, problem, n_traj, seed, arrival,
+                      None if timeout is None else arrival + timeout)
+        req.bytes = self.x.footprint(problem, n_traj)
+        req.n_steps = self.x.steps(problem)
+        if req.bytes > self.alloc.size:
+            req.state = "rejected"
+            self.rejected.append(req)
+            return req
+        self.waiting.append(req)
+        return req
+
+    def cancel(self, tag):
+        """Drop a waiting request, or stop an admitted one at the next window."""
+        for r in list(self.waiting):
+            if r.tag == tag:
+                self.waiting.remove(r)
+                r.state = "cancelled"
+                self.cancelled.append(r)
+                return True
+        for r in self.active:
+            if r.tag == tag:
+                r.state = "cancelling"
+                return True
+        return False
+
+    def admit(self):
+        """Admit waiting requests in arrival order while memory and table
+        slots allow; a request that does not fit yet does not block smaller
+        later ones."""
+        admitted = []
+        now = self.clock()
+        for r in list(self.waiting):
+            if r.deadline is not None and now > r.deadline:
+                self.waiting.remove(r)
+                r.state = "timeout"
+                self.timed_out.append(r)
+                continue
+            if not self.free_slots:
+                break
+            off = self.alloc.alloc(r.bytes)
+            if off is None:
+                continue
+            self.waiting.remove(r)
+            r.offset = off
+            r.slot = self.free_slots.popleft()
+            r.admitted = now
+            try:
+                self.x.init(r)
+            except Exception as e:  # the library refused it: release and report
+                r.error = e
+                r.state = "failed"
+                self._release(r)
+                self.failed.append(r)
+                continue
+            r.state = "active"
+            self.active.append(r)
+            admitted.append(r)
+        self.peak_bytes = max(self.peak_bytes, self.alloc.bytes_used)
+        self.peak_active = max(self.peak_active, len(self.active) + len(self.finishing))
+        return admitted
+
+    # ---------------------------------------------------------- scheduling
+    def remaining(self, r):
+        return r.n_traj * (r.n_steps + 1 - r.k_next)
+
+    def pick(self):
+        """Requests the next window advances."""
+        now = self.clock()
+        for r in self.active:
+            if r.deadline is not None and now > r.deadline and r.state == "active":
+                r.state = "timing_out"
+        run = [r for r in self.active if r.state == "active"]
+        if self.policy == "srpt":
+            run.sort(key=self.remaining)
+            chosen, waves = [], 0
+            for r in run:
+                if waves >= self.fill_waves:
+                    break
+                chosen.append(r)
+                waves += (r.n_traj + 63) // 64
+            run = chosen
+        return run
+
+    def step(self):
+        """One window over the picked requests; requests that reach the end
+        of their pulse are finalised.  Returns the number of requests run."""
+        picked = self.pick()
+        entries = [(r, r.k_next, min(r.k_next + self.window, r.n_steps + 1)) for r in picked]
+        if entries:
+            while len(self._events) >= self.in_flight:
+                self.x.wait(self._events.popleft())
+            self._events.append(self.x.window(entries))
+        for r, _, k_to in entries:
+            r.k_next = k_to
+        still = []
+        for r in self.active:
+            if r.state in ("cancelling", "timing_out"):
+                # queued windows of this request run before any later use of
+                # its memory: every launch goes to the same stream
+                self._release(r)
+                if r.state == "cancelling":
+                    r.state = "cancelled"
+                    self.cancelled.append(r)
+                else:
+                    r.state = "timeout"
+                    self.timed_out.append(r)
+                continue
+            if r.k_next > r.n_steps:
+                r.event = self.x.finalize(r)
+                r.state = "finishing"
+                self.finishing.append(r)
+            else:
+                still.append(r)
+        self.active = still
+        return len(entries)
+
+    def poll(self):
+        """Collect finished requests; returns them."""
+        done = []
+        for r in list(self.finishing):
+            if self.x.done(r.event):
+                r.result = self.x.result(r)
+                r.finished = self.clock()
+                r.state = "done"
+                self.finishing.remove(r)
+                self._release(r)
+                self.completed.append(r)
+                done.append(r)
+        return done
+
+    def _release(self, r):
+        self.alloc.free(r.offset)
+        self.free_slots.append(r.slot)
+
+    @property
+    def busy(self):
+        return bool(self.waiting or self.active or self.finishing)
+
+    def drain(self):
+        while self.busy:
+            self.admit()
+            if self.active:
+                self.step()
+            self.poll()
+
+
+def serve_stream(server, stream, t_limit=None, sleep=time.sleep):
+    """Replay a request stream [(arrival_s, problem, n_traj, seed)] in real
+    time through the server.  Returns the completed requests."""
+    t0 = server.clock()
+    pending = deque(sorted(enumerate(stream), key=lambda x: x[1][0]))
+    while pending or server.busy:
+        now = server.clock() - t0
+        if t_limit is not None and now > t_limit:
+            break
+        while pending and pending[0][1][0] <= now:
+            i, (arr, prob, n, seed) = pending.popleft()
+            server.submit(i, prob, n, seed, arrival=t0 + arr)
+        server.admit()
+        if server.active:
+            server.step()
+        elif not server.finishing and pending:
+            sleep(max(0.0, min(0.01, pending[0][1][0] - (server.clock() - t0))))
+        elif server.finishing:
+            sleep(0.0002)
+        server.poll()
+    return server.completed
+
+
+def fifo_stream(stream, run_one, clock=time.perf_counter, sleep=time.sleep):
+    """Baseline server: requests one at a time, in arrival order, each run to
+    completion by `run_one(problem, n_traj, seed)` before the next starts."""
+    t0 = clock()
+    done = []
+    for i, (arr, prob, n, seed) in sorted(enumerate(stream), key=lambda x: x[1][0]):
+        wait = arr - (clock() - t0)
+        if wait > 0:
+            sleep(wait)
+        r = Request(i, prob, n, seed, t0 + arr)
+        r.admitted = clock()
+        r.result = run_one(prob, n, seed)
+        r.finished = clock()
+        r.state = "done"
+        done.append(r)
+    return done
+
+
+def plain_fp64_runner(h_max, h_step, stream=None):
+    """run_one for fifo_stream: the whole FP64 path of one request (sampling,
+    propagation, dipole, spectrum), synchronised at its end."""
+    import torch
+    from . import run
+
+    def run_one(prob, n, seed):
+        out = run([prob], [n], [seed], precision="fp64", h_max=h_max, h_step=h_step,
+                  stream=stream)
+        torch.cuda.synchronize()
+        return {"v": out["v"][0].cpu(), "yield": out["yield"][0].cpu()}
+
+    return run_one
+
+
+def latency_stats(reqs):
+    lat = sorted(r.finished - r.arrival for r in reqs)
+    if not lat:
+        return {}
+    pick = lambda q: lat[min(len(lat) - 1, int(math.ceil(q * len(lat))) - 1)]
+    return {"n": len(lat), "p50_s": pick(0.50), "p99_s": pick(0.99), "mean_s": sum(lat) / len(lat),
+            "max_s": lat[-1]}

@@ -1,0 +1,180 @@
+"""Serving loop on the device: time-sliced windows of many requests against
+the oracle and the step-wise path; a request gives the same result alone and
+in a mix; admission under a tight pool; cancel and reuse of memory."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+NTHREADS = min(16, os.cpu_count() or 1)
+H_MAX, H_STEP = 30.0, 0.1
+N_OMEGA = int(round(H_MAX / H_STEP)) + 1
+
+
+@pytest.fixture(scope="module")
+def sf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2608_13686_amd as sf
+    return sf
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    r = float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    print(f"relative L2 {r:.3e}", flush=True)
+    return r
+
+
+def server(pool_bytes=1 << 30, max_requests=8, window=1024, policy="ps"):
+    from paper_2608_13686_amd.serve import HipExecutor, Server
+    x = HipExecutor(pool_bytes, max_requests, N_OMEGA, H_STEP)
+    return Server(x, pool_bytes, max_requests=max_requests, window=window, policy=policy)
+
+
+def requests():
+    """Four requests of different problems and sizes.  The last (N2 at 35
+    degrees, seed 9) holds one chaotic trajectory (monodromy norm ~5e20 by
+    the pulse end) that dominates its dipole: no two FP64 implementations
+    agree on it, so it is compared only with the served path itself."""
+    las = dict(workloads.N2_LASER, intensity_wcm2=2.2e14, cep=math.pi / 4)
+    return [(workloads.h2_softcore(0.0), 1500, 1001),
+            (workloads.n2(laser=las, align=workloads.cos2m(2)), 700, 7),
+            (workloads.h2_softcore(align=workloads.cos2m(2),
+                                   laser=dict(workloads.H2_LASER, intensity_wcm2=1.5e14,
+                                              lambda_nm=1000.0, n_cycles=2.0)), 900, 8),
+            (workloads.n2(35.0), 130, 9)]
+
+
+def stepwise(sf, prob, n, seed):
+    import torch
+    out = sf.run([prob], [n], [seed], h_max=H_MAX, h_step=H_STEP)
+    torch.cuda.synchronize()
+    return out["v"][0].cpu().numpy(), out["V"][0].cpu().numpy(), out["yield"][0].cpu().numpy()
+
+
+@pytest.mark.parametrize("window", [64, 777, 1 << 20])
+def test_served_request_matches_oracle(sf, orc, window):
+    prob, n, seed = requests()[0]
+    S = server(window=window)
+    print(f"H2 {n} trajectories, window {window}", flush=True)
+    S.submit("a", prob, n, seed)
+    S.drain()
+    (r,) = S.completed
+    vo, _, _ = orc.dipole(prob, seed, 0, n, NTHREADS)
+    assert rel(r.result["v"].numpy(), vo) < 1e-10
+    N, t0, tau = sf.problem_steps(prob)
+    om = np.arange(N_OMEGA) * H_STEP * 45.56335252912 / prob["laser"]["lambda_nm"]
+    Vo, Yo = orc.spectrum(vo, t0, prob["dt"], 0.5 * tau, om)
+    V = r.result["V_re"].numpy() + 1j * r.result["V_im"].numpy()
+    assert rel(V, Vo) < 1e-10
+    assert rel(r.result["yield"].numpy(), Yo) < 1e-10
+
+
+def test_served_mix_matches_stepwise_path(sf):
+    S = server(window=512)
+    reqs = requests()
+    for i, (p, n, s) in enumerate(reqs):
+        S.submit(i, p, n, s)
+    S.drain()
+    assert len(S.completed) == len(reqs)
+    for r in S.completed:
+        print(f"request {r.tag}", flush=True)
+        if r.tag == 3:  # chaotic: against one served window over the whole pulse
+            S1 = server(window=1 << 20)
+            S1.submit(0, *reqs[3])
+            S1.drain()
+            assert rel(r.result["v"].numpy(), S1.completed[0].result["v"].numpy()) < 1e-12
+            continue
+        v, V, Y = stepwise(sf, *reqs[r.tag])
+        assert rel(r.result["v"].numpy(), v) < 1e-12
+        assert rel(r.result["yield"].numpy(), Y) < 1e-11
+
+
+@pytest.mark.parametrize("policy", ["ps", "srpt"])
+@pytest.mark.parametrize("which", [1, 3])
+def test_request_alone_equals_in_mix(sf, policy, which):
+    """The same request served alone and joined mid-flight by others (which
+    then run windows offset from its own) gives the same dipole; every
+    trajectory takes the same arithmetic alone and in the mix, so even the
+    chaotic request agrees up to the order of the dipole sums."""
+    reqs = requests()
+    others = [i for i in range(len(reqs)) if i != which]
+    S = server(window=300, policy=policy)
+    S.submit("alone", *reqs[which])
+    S.drain()
+    alone = S.completed[0].result
+    S = server(window=300, policy=policy, max_requests=4)
+    S.submit("x0", *reqs[others[0]])
+    S.admit()
+    S.step()
+    S.submit("a", *reqs[which])
+    S.admit()
+    S.step()
+    S.submit("x1", *reqs[others[1]])
+    S.submit("x2", *reqs[others[2]])
+    S.drain()
+    mix = {r.tag: r.result for r in S.completed}
+    assert set(mix) == {"x0", "a", "x1", "x2"}
+    assert rel(mix["a"]["v"].numpy(), alone["v"].numpy()) < 1e-12
+    assert rel(mix["a"]["yield"].numpy(), alone["yield"].numpy()) < 1e-11
+
+
+def test_admission_under_tight_pool(sf):
+    from paper_2608_13686_amd.serve import HipExecutor
+    reqs = requests()[:3]
+    x = HipExecutor(1, 1, N_OMEGA, H_STEP)
+    fp = [x.footprint(p, n) for p, n, _ in reqs]
+    pool = max(fp) + min(fp) + 1024  # at most two requests fit at a time
+    S = server(pool_bytes=pool, max_requests=3, window=700)
+    for i, (p, n, s) in enumerate(reqs):
+        S.submit(i, p, n, s)
+    S.drain()
+    assert len(S.completed) == len(reqs) and S.peak_bytes <= pool
+    for r in S.completed:
+        v, _, _ = stepwise(sf, *reqs[r.tag])
+        assert rel(r.result["v"].numpy(), v) < 1e-12
+
+
+def test_cancel_then_memory_reuse(sf):
+    reqs = requests()
+    S = server(pool_bytes=1 << 28, max_requests=1, window=256)
+    S.submit("cancelled", *reqs[1])
+    S.admit()
+    S.step()
+    S.step()
+    assert S.cancel("cancelled")
+    S.step()
+    S.submit("next", *reqs[0])
+    S.drain()
+    assert [r.tag for r in S.cancelled] == ["cancelled"]
+    (r,) = S.completed
+    v, _, _ = stepwise(sf, *reqs[0])
+    assert rel(r.result["v"].numpy(), v) < 1e-12
+
+
+def test_served_prefactor_cap_matches_oracle(sf, orc):
+    prob = dict(workloads.n2(0.0), c_max=30.0)
+    n, seed = 600, 1002
+    S = server(window=1000)
+    S.submit("capped", prob, n, seed)
+    S.drain()
+    vo, _, _ = orc.dipole(prob, seed, 0, n, NTHREADS)
+    assert rel(S.completed[0].result["v"].numpy(), vo) < 1e-10
+
+
+def test_fifo_runner_matches_served(sf):
+    from paper_2608_13686_amd.serve import plain_fp64_runner
+    prob, n, seed = requests()[2]
+    out = plain_fp64_runner(H_MAX, H_STEP)(prob, n, seed)
+    S = server()
+    S.submit(0, prob, n, seed)
+    S.drain()
+    assert rel(S.completed[0].result["v"].numpy(), out["v"].numpy()) < 1e-12
+    assert rel(S.completed[0].result["yield"].numpy(), out["yield"].numpy()) < 1e-11
