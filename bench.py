@@ -8,9 +8,11 @@ at fixed alignment 0 and 90 degrees, 1200 nm / 1.5e14 W/cm^2 / 4-cycle
 sin^2, dt = 0.05, 1,048,576 trajectories per angle, plain FP64 kernel.
 
 ``variants`` in the same line: the mixed-precision form on the same
-trajectories (with its error against the FP64 run), and the batched
+trajectories (with its error against the FP64 run), the batched
 H2 + N2 cos^4 workload over 64 lasers each (128 x 32,768 trajectories) as
-one tuned persistent plan replayed from a HIP graph.
+one tuned persistent plan replayed from a HIP graph, and a seeded Poisson
+stream of spectrum requests served with continuous batching (two policies)
+beside a FIFO server that runs one request at a time on the plain FP64 path.
 
 Prints one JSON line (metric, value, roofline, cpu_baseline, variants, ...).
 """
@@ -65,7 +67,7 @@ def measured_traffic(kernel_file, workload):
     rec = json.load(open(path))
     csrc = os.path.join(ROOT, "paper_2608_13686_amd", "csrc")
     src = b"".join(open(os.path.join(csrc, f), "rb").read()
-                   for f in ("propagate_f64.hip", "sfhk_internal.h"))
+                   for f in ("propagate_f64.hip", "device_common.h", "sfhk_internal.h"))
     if hashlib.sha256(src).hexdigest() != rec["kernel_sha256"]:
         return None
     return rec["fetch_bytes"] + rec["write_bytes"]
@@ -137,6 +139,53 @@ def timed_plan(sf, probs, n_traj, seeds, precision, tuning, steps, warmup, h_max
     return plan, el / steps
 
 
+def served_variant(sf, n_req, rate_hz, window=1024, h_max=100.0, h_step=0.1):
+    """p50/p99 latency and spectra/s of a seeded Poisson request stream under
+    continuous batching (processor sharing and shortest-remaining-work) and
+    under a FIFO server on the plain FP64 path."""
+    import torch
+    from paper_2608_13686_amd.serve import (HipExecutor, Server, fifo_stream, latency_stats,
+                                            plain_fp64_runner, serve_stream)
+    stream = workloads.request_stream(n_req, rate_hz)
+    n_omega = int(round(h_max / h_step)) + 1
+    pool = 48 << 30
+    x = HipExecutor(pool, 64, n_omega, h_step)
+    # untimed warm-up: one small request through every kernel
+    warm = Server(x, pool, max_requests=64, window=window)
+    warm.submit("warm", stream[0][1], 4096, 1)
+    warm.drain()
+    fifo_warm = plain_fp64_runner(h_max, h_step)
+    fifo_warm(stream[0][1], 4096, 1)
+    torch.cuda.synchronize()
+
+    def summary(done, t_first, wall):
+        st = latency_stats(done)
+        span = max(r.finished for r in done) - t_first
+        return {"completed": len(done), "p50_s": st["p50_s"], "p99_s": st["p99_s"],
+                "mean_s": st["mean_s"], "max_s": st["max_s"], "spectra_per_s": len(done) / span,
+                "wall_s": wall}
+
+    res = {"workload": f"poisson-{n_req}req-{rate_hz:g}hz-seed1004", "n_requests": n_req,
+           "rate_hz": rate_hz, "window_steps": window, "n_omega": n_omega,
+           "trajectories_total": int(sum(n for _, _, n, _ in stream)),
+           "precision": "fp64"}
+    for policy in ("ps", "srpt"):
+        S = Server(x, pool, max_requests=64, window=window, policy=policy)
+        t = time.perf_counter()
+        done = serve_stream(S, stream)
+        wall = time.perf_counter() - t
+        res[f"served_{policy}"] = summary(done, t, wall)
+        res[f"served_{policy}"]["peak_pool_bytes"] = S.peak_bytes
+        res[f"served_{policy}"]["peak_concurrent"] = S.peak_active
+        print(f"served ({policy}): {res[f'served_{policy}']}", file=sys.stderr, flush=True)
+    t = time.perf_counter()
+    done = fifo_stream(stream, plain_fp64_runner(h_max, h_step))
+    wall = time.perf_counter() - t
+    res["fifo_fp64"] = summary(done, t, wall)
+    print(f"fifo: {res['fifo_fp64']}", file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +197,8 @@ def main():
                     help="run one plain device copy of this size first (calibrates HBM counters)")
     ap.add_argument("--no-variants", action="store_true",
                     help="measure only the headline FP64 workload")
+    ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--serve-rate", type=float, default=12.0, help="Poisson arrivals per second")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path shards by trajectory index with one "
@@ -305,6 +356,9 @@ def main():
                                "tuning": list(tun), "launch": "one HIP graph per step"}
         plan.close()
         del plan
+        torch.cuda.empty_cache()
+        if args.serve_requests > 0:
+            variants["served"] = served_variant(sf, args.serve_requests, args.serve_rate)
         out["variants"] = variants
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(probs, seeds)
