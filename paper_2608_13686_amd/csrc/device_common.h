@@ -98,6 +98,68 @@ __device__ __forceinline__ void symmul(const T K[6], const T x[3], T y[3]) {
   y[2] = K[4] * x[0] + K[5] * x[1] + K[2] * x[2];
 }
 
+// Index of element (r, c) of a symmetric 3x3 matrix in the 6-element storage
+// used by symmul: xx, yy, zz, xy, xz, yz.
+__device__ __forceinline__ constexpr int sym_idx(int r, int c) {
+  return r == c ? r : (r + c == 1 ? 3 : (r + c == 2 ? 4 : 5));
+}
+
+// Step matrix of one RK4 step of the monodromy equation.  M' = A(t) M with
+// A = [[0, I], [-K, 0]] is linear, so RK4 with the stage Hessians K1..K4 maps
+// M to P M exactly; expanding the four stages (a product of two A's is block
+// diagonal) gives
+//   P11 = I - h^2/6 (K1 + K2 + K3) + h^4/24 K3 K1
+//   P12 = h I - h^3/12 (K2 + K3)                       (symmetric)
+//   P21 = -h/6 (K1 + 2 K2 + 2 K3 + K4) + h^3/12 (K3 K1 + K4 K2)
+//   P22 = I - h^2/6 (K2 + K3 + K4) + h^4/24 K4 K2.
+// Building P once and applying it to the six columns takes fewer operations
+// than running RK4 on every column.
+template <typename T>
+struct StepMatrix {
+  T a[3][3];  // P11
+  T b[6];     // P12, symmetric storage
+  T c[3][3];  // P21
+  T d[3][3];  // P22
+};
+
+template <typename T>
+__device__ __forceinline__ void rk4_step_matrix(const T K1[6], const T K2[6], const T K3[6],
+                                                const T K4[6], T h, StepMatrix<T>& P) {
+  const T c2 = h * h / T(6), c3 = h * h * h / T(12), c4 = h * h * h * h / T(24), c1 = h / T(6);
+  T s23[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) s23[i] = K2[i] + K3[i];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T q31 = K3[sym_idx(r, 0)] * K1[sym_idx(0, c)] + K3[sym_idx(r, 1)] * K1[sym_idx(1, c)] +
+                    K3[sym_idx(r, 2)] * K1[sym_idx(2, c)];
+      const T q42 = K4[sym_idx(r, 0)] * K2[sym_idx(0, c)] + K4[sym_idx(r, 1)] * K2[sym_idx(1, c)] +
+                    K4[sym_idx(r, 2)] * K2[sym_idx(2, c)];
+      const int i = sym_idx(r, c);
+      const T dl = r == c ? T(1) : T(0);
+      P.a[r][c] = dl - c2 * (K1[i] + s23[i]) + c4 * q31;
+      P.d[r][c] = dl - c2 * (s23[i] + K4[i]) + c4 * q42;
+      P.c[r][c] = c3 * (q31 + q42) - c1 * (K1[i] + K4[i] + T(2) * s23[i]);
+    }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) P.b[i] = (i < 3 ? h : T(0)) - c3 * s23[i];
+}
+
+// One monodromy column (x, v) = (dq/dz_c, dp/dz_c) through the step matrix.
+template <typename T>
+__device__ __forceinline__ void apply_step_matrix(const StepMatrix<T>& P, const T x[3],
+                                                  const T v[3], T xn[3], T vn[3]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    xn[r] = P.a[r][0] * x[0] + P.a[r][1] * x[1] + P.a[r][2] * x[2] + P.b[sym_idx(r, 0)] * v[0] +
+            P.b[sym_idx(r, 1)] * v[1] + P.b[sym_idx(r, 2)] * v[2];
+    vn[r] = P.c[r][0] * x[0] + P.c[r][1] * x[1] + P.c[r][2] * x[2] + P.d[r][0] * v[0] +
+            P.d[r][1] * v[1] + P.d[r][2] * v[2];
+  }
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);

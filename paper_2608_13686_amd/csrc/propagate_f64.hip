@@ -145,56 +145,28 @@ __device__ __forceinline__ void run_pack(const Desc* __restrict__ descs,
       sS += kS;
       S = S + (h / 6.0) * sS;
     }
-    // monodromy: each column (x, v) = (dq/dx0_c, dp/dx0_c) obeys x' = v,
-    // v' = -K(q(t)) x with the stage Hessians K1..K4 of this RK4 step.
-    // Columns c and c + 3 give column c of R.
+    // monodromy: M <- P M with the RK4 step matrix of the stage Hessians
+    // K1..K4 of this step (the exact Jacobian of the discrete RK4 map);
+    // columns c and c + 3 give column c of R.
+    StepMatrix<double> P;
+    rk4_step_matrix(K1, K2, K3, K4, h, P);
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
       __builtin_amdgcn_sched_barrier(0);
       const double x0[3] = {mono[c][lane], mono[6 + c][lane], mono[12 + c][lane]};
       const double v0[3] = {mono[18 + c][lane], mono[24 + c][lane], mono[30 + c][lane]};
-      double a[3], xs[3], vs[3], sx[3], sv[3];
-      symmul(K1, x0, a);
+      double xn[3], vn[3];
+      apply_step_matrix(P, x0, v0, xn, vn);
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
-        sx[r] = v0[r];
-        sv[r] = -a[r];
-        xs[r] = x0[r] + 0.5 * h * v0[r];
-        vs[r] = v0[r] + 0.5 * h * (-a[r]);
-      }
-      symmul(K2, xs, a);
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const double kx = vs[r];
-        sx[r] += 2.0 * kx;
-        sv[r] += 2.0 * (-a[r]);
-        xs[r] = x0[r] + 0.5 * h * kx;
-        vs[r] = v0[r] + 0.5 * h * (-a[r]);
-      }
-      symmul(K3, xs, a);
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const double kx = vs[r];
-        sx[r] += 2.0 * kx;
-        sv[r] += 2.0 * (-a[r]);
-        xs[r] = x0[r] + h * kx;
-        vs[r] = v0[r] + h * (-a[r]);
-      }
-      symmul(K4, xs, a);
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        sx[r] += vs[r];
-        sv[r] += -a[r];
-        const double xn = x0[r] + (h / 6.0) * sx[r];
-        const double vn = v0[r] + (h / 6.0) * sv[r];
-        mono[6 * r + c][lane] = xn;
-        mono[18 + 6 * r + c][lane] = vn;
+        mono[6 * r + c][lane] = xn[r];
+        mono[18 + 6 * r + c][lane] = vn[r];
         if (c < 3) {  // x = Mqq[:, c], v = Mpq[:, c]
-          Rr[r][c] = 0.5 * xn;
-          Ri[r][c] = 0.5 * d.inv_gamma * vn;
+          Rr[r][c] = 0.5 * xn[r];
+          Ri[r][c] = 0.5 * d.inv_gamma * vn[r];
         } else {      // x = Mqp[:, c-3], v = Mpp[:, c-3]
-          Rr[r][c - 3] += 0.5 * vn;
-          Ri[r][c - 3] -= 0.5 * d.gamma * xn;
+          Rr[r][c - 3] += 0.5 * vn[r];
+          Ri[r][c - 3] -= 0.5 * d.gamma * xn[r];
         }
       }
     }
