@@ -139,7 +139,7 @@ def timed_plan(sf, probs, n_traj, seeds, precision, tuning, steps, warmup, h_max
     return plan, el / steps
 
 
-def served_variant(sf, n_req, rate_hz, window=1024, h_max=100.0, h_step=0.1):
+def served_variant(sf, n_req, rate_hz, window=1024, h_max=100.0, h_step=0.1, n_groups=2):
     """p50/p99 latency and spectra/s of a seeded Poisson request stream under
     continuous batching (processor sharing and shortest-remaining-work) and
     under a FIFO server on the plain FP64 path."""
@@ -149,7 +149,7 @@ def served_variant(sf, n_req, rate_hz, window=1024, h_max=100.0, h_step=0.1):
     stream = workloads.request_stream(n_req, rate_hz)
     n_omega = int(round(h_max / h_step)) + 1
     pool = 48 << 30
-    x = HipExecutor(pool, 64, n_omega, h_step)
+    x = HipExecutor(pool, 64, n_omega, h_step, n_groups=n_groups)
     # untimed warm-up: one small request through every kernel
     warm = Server(x, pool, max_requests=64, window=window)
     warm.submit("warm", stream[0][1], 4096, 1)
@@ -166,7 +166,8 @@ def served_variant(sf, n_req, rate_hz, window=1024, h_max=100.0, h_step=0.1):
                 "wall_s": wall}
 
     res = {"workload": f"poisson-{n_req}req-{rate_hz:g}hz-seed1004", "n_requests": n_req,
-           "rate_hz": rate_hz, "window_steps": window, "n_omega": n_omega,
+           "rate_hz": rate_hz, "window_steps": window, "pack_groups": n_groups,
+           "n_omega": n_omega,
            "trajectories_total": int(sum(n for _, _, n, _ in stream)),
            "precision": "fp64"}
     for policy in ("ps", "srpt"):

@@ -300,13 +300,16 @@ sfhk_status sfhk_request_init(const sfhk_problem* p, uint64_t n_traj, uint64_t s
                               int32_t slot, void* stream);
 
 /* Advance n admitted requests by one window each: request slots[i] over its
- * steps [k_from[i], k_to[i]) (windows of one request must be launched in
- * order and without gaps, starting at 0); n_traj[i] is its trajectory count
- * (a larger value only launches idle wavefronts, a smaller one drops packs).
- * The same physics as sfhk_propagate in FP64 (Sec. II.A; Eq. 4-6). */
+ * steps [k_from[i], k_to[i]); n_traj[i] is its trajectory count (a larger
+ * value only launches idle wavefronts, a smaller one drops packs).  The
+ * launch covers pack group `group` of every request: its packs group,
+ * group + n_groups, ... (0 <= group < n_groups <= 64).  Each pack group of a
+ * request advances on its own: its windows must be launched in order, without
+ * gaps, starting at 0, so different groups may be on different streams.  The
+ * same physics as sfhk_propagate in FP64 (Sec. II.A; Eq. 4-6). */
 sfhk_status sfhk_serve_window(void* table, int32_t table_slots, int32_t n, const int32_t* slots,
                               const uint64_t* n_traj, const int32_t* k_from, const int32_t* k_to,
-                              void* stream);
+                              int32_t group, int32_t n_groups, void* stream);
 
 /* Dipole (v = 2 accum / n_traj) and spectrum of a request whose windows have
  * covered steps 0..N; results at sfhk_request_layout's offsets. */

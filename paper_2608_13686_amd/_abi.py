@@ -122,7 +122,7 @@ def lib():
         L.sfhk_request_init.restype = C.c_int
         i32p = C.POINTER(C.c_int32)
         L.sfhk_serve_window.argtypes = [C.c_void_p, C.c_int32, C.c_int32, i32p, u64p, i32p,
-                                        i32p, C.c_void_p]
+                                        i32p, C.c_int32, C.c_int32, C.c_void_p]
         L.sfhk_serve_window.restype = C.c_int
         L.sfhk_request_finalize.argtypes = [P, C.c_int32, C.c_void_p, C.c_int32, C.c_int32,
                                             C.c_void_p]

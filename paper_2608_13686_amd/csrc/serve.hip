@@ -11,7 +11,8 @@ namespace {
 
 constexpr int kMonoElems = 36;
 
-// one wavefront per (request, pack); the window table is a kernel argument
+// one wavefront per (request, pack of the launch's pack group); the window
+// table is a kernel argument
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2)))
 serve_slice_f64(const ReqDev* __restrict__ reqs, SliceTable tab) {
   __shared__ double mono[kMonoElems][kWave];
@@ -26,7 +27,7 @@ serve_slice_f64(const ReqDev* __restrict__ reqs, SliceTable tab) {
   const SliceEntry se = tab.e[lo];
   const ReqDev& R = reqs[se.slot];
   const Desc& d = R.desc;
-  const uint32_t pack = w - se.pack_begin;
+  const uint32_t pack = tab.group + (w - se.pack_begin) * tab.n_groups;
   if (pack >= R.pack_start[1]) return;
   const int N = d.N;
   const uint32_t pos = pack * kWave + lane;

@@ -155,20 +155,25 @@ sfhk_status sfhk_request_init(const sfhk_problem* p, uint64_t n_traj, uint64_t s
 
 sfhk_status sfhk_serve_window(void* table, int32_t table_slots, int32_t n, const int32_t* slots,
                               const uint64_t* n_traj, const int32_t* k_from, const int32_t* k_to,
-                              void* stream) {
+                              int32_t group, int32_t n_groups, void* stream) {
   if (!table || n < 0 || (n > 0 && (!slots || !n_traj || !k_from || !k_to)))
     return fail_ext(SFHK_E_INVALID, "window arguments invalid");
+  if (n_groups < 1 || n_groups > 64 || group < 0 || group >= n_groups)
+    return fail_ext(SFHK_E_INVALID, "pack group must satisfy 0 <= group < n_groups <= 64");
   hipStream_t s = static_cast<hipStream_t>(stream);
   int i = 0;
   while (i < n) {  // at most kMaxSlice requests per launch
     SliceTable tab;
     std::memset(&tab, 0, sizeof tab);
+    tab.group = (uint16_t)group;
+    tab.n_groups = (uint16_t)n_groups;
     uint32_t waves = 0;
     int m = 0;
     for (; i < n && m < kMaxSlice; ++i, ++m) {
       if (slots[i] < 0 || slots[i] >= table_slots || k_from[i] < 0 || k_to[i] <= k_from[i])
         return fail_ext(SFHK_E_INVALID, "window entry invalid");
-      const uint64_t packs = (n_traj[i] + kWave - 1) / kWave;
+      const uint64_t all = (n_traj[i] + kWave - 1) / kWave;  // packs of the request
+      const uint64_t packs = all > (uint64_t)group ? (all - group + n_groups - 1) / n_groups : 0;
       // the launch holds waves * 64 work-items, which must stay below 2^32
       if ((uint64_t)waves + packs > 0xffffffffull / kWave)
         return fail_ext(SFHK_E_UNSUPPORTED, "window too large");

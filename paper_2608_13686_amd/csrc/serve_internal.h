@@ -34,8 +34,11 @@ struct SliceEntry {
   int32_t k_from, k_to; // window of steps [k_from, k_to)
 };
 
+// A launch covers one pack group of every listed request: the packs
+// group, group + n_groups, group + 2 n_groups, ... of each request.
 struct SliceTable {
-  int32_t n, pad;
+  int32_t n;
+  uint16_t group, n_groups;
   SliceEntry e[kMaxSlice + 1];  // e[n].pack_begin = total wavefronts
 };
 static_assert(sizeof(SliceTable) <= 2048, "SliceTable is a kernel argument");

@@ -91,9 +91,13 @@ class Request:
 
 class HipExecutor:
     """Device side of the server: a torch uint8 pool, the request table and
-    the C ABI calls, all on one torch stream."""
+    the C ABI calls.  Requests are sampled and finalised on the main stream;
+    their packs are split into `n_groups` interleaved groups, each advanced by
+    its own stream, so that the tail of one group's window overlaps the
+    others' windows.  All streams have the default priority."""
 
-    def __init__(self, pool_bytes, max_requests, n_omega, h_step, device="cuda", stream=None):
+    def __init__(self, pool_bytes, max_requests, n_omega, h_step, device="cuda", stream=None,
+                 n_groups=2):
         import torch
         self.torch = torch
         self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=device)
@@ -104,6 +108,8 @@ class HipExecutor:
         self.h_step = h_step
         self.stream = stream or torch.cuda.current_stream()
         self._h = C.c_void_p(self.stream.cuda_stream)
+        self.n_groups = int(n_groups)
+        self.group_streams = [torch.cuda.Stream(device=device) for _ in range(self.n_groups)]
 
     def footprint(self, problem, n_traj):
         arr = _abi.make_problems([problem])
@@ -116,6 +122,11 @@ class HipExecutor:
         from . import problem_steps
         return problem_steps(problem)[0]
 
+    def _event(self, stream):
+        ev = self.torch.cuda.Event()
+        ev.record(stream)
+        return ev
+
     def init(self, req):
         req.handle = arr = _abi.make_problems([req.problem])
         _abi.check(_abi.lib().sfhk_request_init(
@@ -123,28 +134,37 @@ class HipExecutor:
             C.c_void_p(self.pool.data_ptr() + req.offset), req.bytes,
             C.c_void_p(self.table.data_ptr()), self.max_requests, req.slot, self._h),
             "sfhk_request_init")
+        ev = self._event(self.stream)
+        for gs in self.group_streams:
+            gs.wait_event(ev)
 
-    def window(self, entries):
-        """entries: list of (request, k_from, k_to)."""
+    def window(self, entries, group=0):
+        """entries: list of (request, k_from, k_to); advances pack group `group`."""
         n = len(entries)
         slots = (C.c_int32 * n)(*[r.slot for r, _, _ in entries])
         ntraj = (C.c_uint64 * n)(*[r.n_traj for r, _, _ in entries])
         kf = (C.c_int32 * n)(*[a for _, a, _ in entries])
         kt = (C.c_int32 * n)(*[b for _, _, b in entries])
+        gs = self.group_streams[group]
         _abi.check(_abi.lib().sfhk_serve_window(C.c_void_p(self.table.data_ptr()),
                                                 self.max_requests, n, slots, ntraj, kf, kt,
-                                                self._h), "sfhk_serve_window")
-        ev = self.torch.cuda.Event()
-        ev.record(self.stream)
-        return ev
+                                                group, self.n_groups,
+                                                C.c_void_p(gs.cuda_stream)), "sfhk_serve_window")
+        return self._event(gs)
 
     def finalize(self, req):
+        for gs in self.group_streams:
+            self.stream.wait_event(self._event(gs))
         _abi.check(_abi.lib().sfhk_request_finalize(
             req.handle, self.n_omega, C.c_void_p(self.table.data_ptr()),
             self.max_requests, req.slot, self._h), "sfhk_request_finalize")
-        ev = self.torch.cuda.Event()
-        ev.record(self.stream)
-        return ev
+        return self._event(self.stream)
+
+    def retire(self, req):
+        """Event after which no queued work touches the request's memory."""
+        for gs in self.group_streams:
+            self.stream.wait_event(self._event(gs))
+        return self._event(self.stream)
 
     def done(self, ev):
         return ev.query()
@@ -177,10 +197,16 @@ class Server:
     sharing); ``"srpt"`` advances the requests with the least remaining work
     (trajectories x steps left) first, adding requests until the launch holds
     at least `fill_waves` wavefronts, so the device stays full while short
-    requests overtake long ones."""
+    requests overtake long ones.
+
+    A launch with fewer wavefronts than the device keeps resident
+    (`device_waves`, 2 per SIMD on 1,024 SIMDs) leaves the device partly idle
+    whatever its length, and each window costs a tail; such launches run
+    windows up to `max_stretch` times longer (in proportion to the idle room)."""
 
     def __init__(self, executor, pool_bytes, max_requests=64, window=1024, in_flight=2,
-                 policy="ps", fill_waves=16384, clock=time.perf_counter):
+                 policy="ps", fill_waves=16384, device_waves=2048, max_stretch=8,
+                 clock=time.perf_counter):
         if policy not in ("ps", "srpt"):
             raise ValueError("policy must be 'ps' or 'srpt'")
         if window < 1 or in_flight < 1 or max_requests < 1:
@@ -192,18 +218,22 @@ class Server:
         self.in_flight = in_flight
         self.policy = policy
         self.fill_waves = int(fill_waves)
+        self.device_waves = int(device_waves)
+        self.max_stretch = max(1, int(max_stretch))
         self.clock = clock
         self.failed = []
         self.timed_out = []
         self.cancelled = []
         self.peak_bytes = 0
         self.peak_active = 0
+        self.n_groups = int(getattr(executor, "n_groups", 1))
+        self._events = [deque() for _ in range(self.n_groups)]
+        self.retiring = []
         self.waiting = deque()
         self.active = []
         self.finishing = []
         self.completed = []
         self.rejected = []
-        self._events = deque()
 
     # ------------------------------------------------------------ requests
     def submit(self, tag, problem, n_traj, seed, arrival=None, timeout=None):
@@ -293,29 +323,39 @@ class Server:
             run = chosen
         return run
 
+    def window_for(self, picked):
+        """Window length of the next launch (steps)."""
+        waves = sum((r.n_traj + 63) // 64 for r in picked)
+        stretch = min(self.max_stretch, max(1, self.device_waves // max(waves, 1)))
+        return self.window * stretch
+
     def step(self):
-        """One window over the picked requests; requests that reach the end
-        of their pulse are finalised.  Returns the number of requests run."""
+        """One window over the picked requests, launched for every pack group;
+        requests that reach the end of their pulse are finalised.  Returns the
+        number of requests run."""
         picked = self.pick()
-        entries = [(r, r.k_next, min(r.k_next + self.window, r.n_steps + 1)) for r in picked]
+        win = self.window_for(picked)
+        entries = [(r, r.k_next, min(r.k_next + win, r.n_steps + 1)) for r in picked]
         if entries:
-            while len(self._events) >= self.in_flight:
-                self.x.wait(self._events.popleft())
-            self._events.append(self.x.window(entries))
+            for g in range(self.n_groups):
+                evs = self._events[g]
+                while len(evs) >= self.in_flight:
+                    self.x.wait(evs.popleft())
+                evs.append(self.x.window(entries, g))
         for r, _, k_to in entries:
             r.k_next = k_to
         still = []
         for r in self.active:
             if r.state in ("cancelling", "timing_out"):
-                # queued windows of this request run before any later use of
-                # its memory: every launch goes to the same stream
-                self._release(r)
+                # its memory is released once the work queued for it is done
+                r.event = self.x.retire(r)
                 if r.state == "cancelling":
                     r.state = "cancelled"
                     self.cancelled.append(r)
                 else:
                     r.state = "timeout"
                     self.timed_out.append(r)
+                self.retiring.append(r)
                 continue
             if r.k_next > r.n_steps:
                 r.event = self.x.finalize(r)
@@ -327,7 +367,12 @@ class Server:
         return len(entries)
 
     def poll(self):
-        """Collect finished requests; returns them."""
+        """Collect finished requests and release retired ones; returns the
+        finished requests."""
+        for r in list(self.retiring):
+            if self.x.done(r.event):
+                self.retiring.remove(r)
+                self._release(r)
         done = []
         for r in list(self.finishing):
             if self.x.done(r.event):
@@ -346,7 +391,7 @@ class Server:
 
     @property
     def busy(self):
-        return bool(self.waiting or self.active or self.finishing)
+        return bool(self.waiting or self.active or self.finishing or self.retiring)
 
     def drain(self):
         while self.busy:

@@ -32,9 +32,9 @@ def rel(a, b):
     return r
 
 
-def server(pool_bytes=1 << 30, max_requests=8, window=1024, policy="ps"):
+def server(pool_bytes=1 << 30, max_requests=8, window=1024, policy="ps", n_groups=2):
     from paper_2608_13686_amd.serve import HipExecutor, Server
-    x = HipExecutor(pool_bytes, max_requests, N_OMEGA, H_STEP)
+    x = HipExecutor(pool_bytes, max_requests, N_OMEGA, H_STEP, n_groups=n_groups)
     return Server(x, pool_bytes, max_requests=max_requests, window=window, policy=policy)
 
 
@@ -59,11 +59,11 @@ def stepwise(sf, prob, n, seed):
     return out["v"][0].cpu().numpy(), out["V"][0].cpu().numpy(), out["yield"][0].cpu().numpy()
 
 
-@pytest.mark.parametrize("window", [64, 777, 1 << 20])
-def test_served_request_matches_oracle(sf, orc, window):
+@pytest.mark.parametrize("window,n_groups", [(64, 1), (777, 3), (1 << 20, 2)])
+def test_served_request_matches_oracle(sf, orc, window, n_groups):
     prob, n, seed = requests()[0]
-    S = server(window=window)
-    print(f"H2 {n} trajectories, window {window}", flush=True)
+    S = server(window=window, n_groups=n_groups)
+    print(f"H2 {n} trajectories, window {window}, {n_groups} pack groups", flush=True)
     S.submit("a", prob, n, seed)
     S.drain()
     (r,) = S.completed
@@ -87,7 +87,7 @@ def test_served_mix_matches_stepwise_path(sf):
     for r in S.completed:
         print(f"request {r.tag}", flush=True)
         if r.tag == 3:  # chaotic: against one served window over the whole pulse
-            S1 = server(window=1 << 20)
+            S1 = server(window=1 << 20, n_groups=1)
             S1.submit(0, *reqs[3])
             S1.drain()
             assert rel(r.result["v"].numpy(), S1.completed[0].result["v"].numpy()) < 1e-12

@@ -55,12 +55,15 @@ def test_allocator_coalesces_neighbours():
 
 # -------------------------------------------------------------- fake executor
 class FakeExec:
-    """Host-only executor: records every call and checks that concurrently
-    admitted requests never share memory or a table slot."""
+    """Host-only executor with two pack groups: records every call and checks
+    that concurrently admitted requests never share memory or a table slot."""
+
+    n_groups = 2
 
     def __init__(self, fail_tags=()):
         self.windows = {}
         self.finalized = []
+        self.retired = []
         self.launches = []
         self.live = {}
         self.fail_tags = set(fail_tags)
@@ -79,18 +82,23 @@ class FakeExec:
             assert slot != r.slot
             assert r.offset + r.bytes <= off or off + nb <= r.offset
         self.live[r.tag] = (r.offset, r.bytes, r.slot)
-        self.windows[r.tag] = []
+        self.windows[r.tag] = {g: [] for g in range(self.n_groups)}
 
-    def window(self, entries):
-        assert entries
-        self.launches.append([(r.tag, a, b) for r, a, b in entries])
+    def window(self, entries, group=0):
+        assert entries and 0 <= group < self.n_groups
+        self.launches.append((group, [(r.tag, a, b) for r, a, b in entries]))
         for r, a, b in entries:
             assert r.tag in self.live
-            self.windows[r.tag].append((a, b))
+            self.windows[r.tag][group].append((a, b))
         return len(self.launches)
 
     def finalize(self, r):
         self.finalized.append(r.tag)
+        self.live.pop(r.tag)
+        return 0
+
+    def retire(self, r):
+        self.retired.append(r.tag)
         self.live.pop(r.tag)
         return 0
 
@@ -101,7 +109,9 @@ class FakeExec:
         self.waits += 1
 
     def result(self, r):
-        return {"windows": list(self.windows[r.tag])}
+        w = self.windows[r.tag]
+        assert all(w[g] == w[0] for g in w), "pack groups advanced differently"
+        return {"windows": list(w[0])}
 
 
 def _prob(N):
@@ -110,7 +120,7 @@ def _prob(N):
 
 def test_server_windows_cover_each_request_once():
     x = FakeExec()
-    S = Server(x, pool_bytes=1 << 22, max_requests=4, window=100, in_flight=2)
+    S = Server(x, pool_bytes=1 << 22, max_requests=4, window=100, in_flight=2, max_stretch=1)
     sizes = [(250, 1000), (99, 64), (1000, 3000), (100, 5), (0, 10), (333, 7000)]
     for i, (N, n) in enumerate(sizes):
         S.submit(i, _prob(N), n, seed=i)
@@ -124,8 +134,8 @@ def test_server_windows_cover_each_request_once():
     assert sorted(x.finalized) == list(range(len(sizes)))
     assert S.peak_active <= 4 and not x.live
     assert S.alloc.free_list == [(0, 1 << 22)]
-    # at most in_flight launches are ever outstanding
-    assert x.waits >= len(x.launches) - 2
+    # at most in_flight launches per pack group are ever outstanding
+    assert x.waits >= len(x.launches) - 2 * x.n_groups
 
 
 def test_admission_never_exceeds_pool_and_slots():
@@ -177,7 +187,7 @@ def test_cancel_waiting_and_active():
     S.step()
     S.drain()
     assert {r.tag for r in S.cancelled} == {"run", "wait"}
-    assert not S.completed and not x.finalized
+    assert not S.completed and not x.finalized and x.retired == ["run"]
     assert S.alloc.bytes_used == 0 and len(S.free_slots) == 1
 
 
@@ -218,7 +228,8 @@ def test_srpt_picks_least_remaining_work_and_fills():
     S.submit("mid", _prob(1000), 640, 2)
     S.admit()
     S.step()
-    assert [t for t, _, _ in x.launches[0]] == ["short", "mid"]
+    assert [t for t, _, _ in x.launches[0][1]] == ["short", "mid"]
+    assert x.launches[1][0] == 1 and x.launches[1][1] == x.launches[0][1]
     S.drain()
     assert [r.tag for r in S.completed][:2] == ["short", "mid"]
 
@@ -245,6 +256,23 @@ def test_serve_stream_and_fifo_with_fake_clock():
     fifo = fifo_stream(stream, lambda p, n, s: {"n": n}, clock=clock, sleep=sleep)
     assert [r.tag for r in fifo] == list(range(12))
     assert all(r.finished >= r.arrival for r in fifo)
+
+
+def test_small_launches_stretch_their_window():
+    x = FakeExec()
+    S = Server(x, pool_bytes=1 << 26, max_requests=4, window=100, device_waves=64,
+               max_stretch=8)
+    S.submit("small", _prob(5000), 64 * 10, 0)   # 10 waves: window x 6
+    S.admit()
+    S.step()
+    assert x.launches[0][1] == [("small", 0, 600)]
+    S.submit("big", _prob(5000), 64 * 100, 1)    # with it, 110 waves: no stretch
+    S.admit()
+    S.step()
+    assert x.launches[-1][1] == [("small", 600, 700), ("big", 0, 100)]
+    S.drain()
+    w = S.completed[0].result["windows"]
+    assert w[-1][1] == 5001 and all(w[i][1] == w[i + 1][0] for i in range(len(w) - 1))
 
 
 def test_server_rejects_bad_config():
@@ -289,12 +317,16 @@ def test_request_entry_points_reject_bad_arguments():
     assert L.sfhk_request_init(p, 1000, 1, 0, -0.1, 10, fake, nb, fake, 4, 0, None) == E_INVALID
     one = (C.c_int32 * 1)
     n64 = (C.c_uint64 * 1)(1000)
-    assert L.sfhk_serve_window(fake, 4, 1, one(4), n64, one(0), one(10), None) == E_INVALID
-    assert L.sfhk_serve_window(fake, 4, 1, one(0), n64, one(10), one(10), None) == E_INVALID
-    assert L.sfhk_serve_window(fake, 4, 1, one(0), n64, one(-1), one(10), None) == E_INVALID
-    assert L.sfhk_serve_window(None, 4, 0, None, None, None, None, None) == E_INVALID
-    assert L.sfhk_serve_window(fake, 4, 0, None, None, None, None, None) == 0  # nothing to do
+    win = L.sfhk_serve_window
+    assert win(fake, 4, 1, one(4), n64, one(0), one(10), 0, 1, None) == E_INVALID
+    assert win(fake, 4, 1, one(0), n64, one(10), one(10), 0, 1, None) == E_INVALID
+    assert win(fake, 4, 1, one(0), n64, one(-1), one(10), 0, 1, None) == E_INVALID
+    assert win(fake, 4, 1, one(0), n64, one(0), one(10), 2, 2, None) == E_INVALID  # group >= n
+    assert win(fake, 4, 1, one(0), n64, one(0), one(10), 0, 0, None) == E_INVALID
+    assert win(fake, 4, 1, one(0), n64, one(0), one(10), 0, 65, None) == E_INVALID
+    assert win(None, 4, 0, None, None, None, None, 0, 1, None) == E_INVALID
+    assert win(fake, 4, 0, None, None, None, None, 0, 1, None) == 0  # nothing to do
     big = (C.c_uint64 * 1)(1 << 40)
-    assert L.sfhk_serve_window(fake, 4, 1, one(0), big, one(0), one(10), None) == 5
+    assert win(fake, 4, 1, one(0), big, one(0), one(10), 0, 1, None) == 5
     assert L.sfhk_request_finalize(p, 10, fake, 4, 4, None) == E_INVALID
     assert L.sfhk_request_finalize(p, -1, fake, 4, 0, None) == E_INVALID
