@@ -32,7 +32,10 @@ class Problem(C.Structure):
         ("sigma_perp", C.c_double),
         ("n_steps", C.c_int32),
         ("c_max", C.c_double),
+        ("ionization", C.c_int32),
     ]
+
+IONIZATION = {"first_order": 0, "saddle": 1}
 
 
 _lib = None
@@ -56,9 +59,12 @@ def lib():
         u32p = C.POINTER(C.c_uint32)
         L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
         L.orc_sample.argtypes = [P, C.c_uint64, C.c_uint64, C.c_uint64,
-                                 C.POINTER(C.c_int32), dp, dp, dp, dp]
+                                 C.POINTER(C.c_int32), dp, dp, dp, dp, dp]
         L.orc_trajectory.argtypes = [P, C.c_int32, C.c_int32, dp, dp, dp, C.c_double,
-                                     dp, dp, dp, dp, dp]
+                                     C.c_double, dp, dp, dp, dp, dp]
+        L.orc_sfa_step.argtypes = [P, C.c_double, dp, dp, dp]
+        L.orc_sfa_step.restype = C.c_int
+        L.orc_field_complex.argtypes = [P, C.c_double, C.c_double, dp, dp, dp, dp]
         L.orc_trajectory.restype = C.c_int
         L.orc_run.argtypes = [P, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int32, dp,
                               C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
@@ -113,6 +119,7 @@ def make_problem(d):
     P.sigma_perp = d["sigma_perp"]
     P.n_steps = int(d.get("n_steps", 0))
     P.c_max = float(d.get("c_max", 0.0))
+    P.ionization = IONIZATION[d.get("ionization", "first_order")]
     return P
 
 
@@ -188,19 +195,42 @@ def philox(ctr, key):
 
 
 def sample(d, seed, first, n):
-    """dict of k0 [n], q0 [n,3], p0 [n,3], nax [n,3], w [n] for trajectories first..first+n-1."""
+    """dict of k0 [n], q0 [n,3], p0 [n,3], nax [n,3], w [n], dph [n] for
+    trajectories first..first+n-1."""
     P = make_problem(d)
     k0 = np.zeros(n, dtype=np.int32)
     q0 = np.zeros((n, 3))
     p0 = np.zeros((n, 3))
     nax = np.zeros((n, 3))
     w = np.zeros(n)
+    dph = np.zeros(n)
     lib().orc_sample(C.byref(P), int(seed), int(first), int(n),
-                     k0.ctypes.data_as(C.POINTER(C.c_int32)), _dp(q0), _dp(p0), _dp(nax), _dp(w))
-    return {"k0": k0, "q0": q0, "p0": p0, "nax": nax, "w": w}
+                     k0.ctypes.data_as(C.POINTER(C.c_int32)), _dp(q0), _dp(p0), _dp(nax), _dp(w),
+                     _dp(dph))
+    return {"k0": k0, "q0": q0, "p0": p0, "nax": nax, "w": w, "dph": dph}
 
 
-def trajectory(d, k0, q0, p0, nax, w=1.0, k_end=None, amplitudes=True, prefactors=False):
+def sfa_step(d, t0, kperp, nax):
+    """Exact SFA ionisation step: dict(tt, kz, q0z, S (complex), m (complex)) or None."""
+    P = make_problem(d)
+    out = np.zeros(7)
+    kp, n = _arr(kperp, 2), _arr(nax, 3)
+    if lib().orc_sfa_step(C.byref(P), float(t0), _dp(kp), _dp(n), _dp(out)) != 0:
+        return None
+    return {"tt": out[0], "kz": out[1], "q0z": out[2], "S": complex(out[3], out[4]),
+            "m": complex(out[5], out[6])}
+
+
+def field_complex(d, tr, ti):
+    """(A, E) of the laser at complex time tr + i ti."""
+    P = make_problem(d)
+    v = [C.c_double() for _ in range(4)]
+    lib().orc_field_complex(C.byref(P), float(tr), float(ti), *[C.byref(x) for x in v])
+    return complex(v[0].value, v[1].value), complex(v[2].value, v[3].value)
+
+
+def trajectory(d, k0, q0, p0, nax, w=1.0, k_end=None, amplitudes=True, prefactors=False,
+               dph=0.0):
     """Propagate one trajectory; returns (a [N+1] complex or None, final [NFINAL]),
     plus C [N+1] complex when prefactors=True."""
     P = make_problem(d)
@@ -215,7 +245,7 @@ def trajectory(d, k0, q0, p0, nax, w=1.0, k_end=None, amplitudes=True, prefactor
     cim = np.zeros(N + 1) if prefactors else None
     ptr = lambda a: _dp(a) if a is not None else None
     rc = lib().orc_trajectory(C.byref(P), int(k0), int(k_end), _dp(q), _dp(p), _dp(n), float(w),
-                              ptr(are), ptr(aim), ptr(cre), ptr(cim), _dp(fin))
+                              float(dph), ptr(are), ptr(aim), ptr(cre), ptr(cim), _dp(fin))
     if rc != 0:
         raise ValueError("orc_trajectory rejected its arguments")
     a = (are + 1j * aim) if amplitudes else None

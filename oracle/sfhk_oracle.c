@@ -166,6 +166,179 @@ void orc_prefactor_det(const double M[36], double gamma, double* re, double* im)
   *im = cimag(d);
 }
 
+/* ------------------------------------------------- SFA ionisation step */
+/* The laser continued to complex time: the inside-pulse formula of the
+ * laser reading above, A(t) = -(E0/w) cos^2(pi t/tau) sin(w t + cep) and
+ * E = -dA/dt, evaluated for complex t (the saddle point t_s = t0 + i t_t of
+ * Eq. (2) has its real part inside the pulse). */
+static double complex vecpot_c(const orc_problem* P, double complex t) {
+  double w, e0, tau;
+  orc_laser(P, &w, &e0, &tau, NULL);
+  double complex env = ccos(ORC_PI * t / tau);
+  return -(e0 / w) * env * env * csin(w * t + P->cep);
+}
+
+static double complex field_c(const orc_problem* P, double complex t) {
+  double w, e0, tau;
+  orc_laser(P, &w, &e0, &tau, NULL);
+  double complex env = ccos(ORC_PI * t / tau);
+  double complex ph = w * t + P->cep;
+  return e0 * env * env * ccos(ph) -
+         (e0 * ORC_PI / (w * tau)) * csin(2.0 * ORC_PI * t / tau) * csin(ph);
+}
+
+void orc_field_complex(const orc_problem* P, double tr, double ti, double* A_re, double* A_im,
+                       double* E_re, double* E_im) {
+  double complex t = tr + I * ti;
+  double complex A = vecpot_c(P, t), E = field_c(P, t);
+  if (A_re) *A_re = creal(A);
+  if (A_im) *A_im = cimag(A);
+  if (E_re) *E_re = creal(E);
+  if (E_im) *E_im = cimag(E);
+}
+
+/* Legendre polynomial P_n(z) and its derivative, by the three-term recurrence */
+static void legendre(int n, double z, double* p, double* dp) {
+  double p0 = 1.0, p1 = z;
+  for (int k = 2; k <= n; ++k) {
+    double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  *p = p1;
+  *dp = n * (z * p1 - p0) / (z * z - 1.0);
+}
+
+/* 16-point Gauss-Legendre nodes (roots of P_16, by Newton's method) and
+ * weights 2 / ((1 - z^2) P_16'(z)^2) on [-1, 1] */
+static void gauss_legendre16(double x[16], double wt[16]) {
+  const int n = 16;
+  for (int i = 0; i < n; ++i) {
+    double z = cos(ORC_PI * (i + 0.75) / (n + 0.5)), p, dp;
+    for (int it = 0; it < 100; ++it) {
+      legendre(n, z, &p, &dp);
+      double dz = p / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-15) break;
+    }
+    legendre(n, z, &p, &dp);
+    x[i] = z;
+    wt[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+/* Saddle point of Eq. (2) for birth time t0 = Re t_s and transverse momentum
+ * k_perp: [k + A(t_s) - A(t0)]^2 / 2 + I_p = 0 with k real.  Writing
+ * kappa_z(t) = k_z + A(t) - A(t0), the equation is
+ * kappa_z(t_s) = -/+ i sqrt(2 I_p + k_perp^2), i.e. two real conditions:
+ *   Im A(t0 + i t_t) = -sgn E(t0) sqrt(2 I_p + k_perp^2)   (fixes t_t > 0),
+ *   k_z = A(t0) - Re A(t0 + i t_t)                           (fixes k_z).
+ * Reading: the root with the smallest t_t > 0 (the saddle point closest to
+ * the real axis), found by stepping t_t by 1 a.u. from 0 up to 150 a.u. to
+ * the first crossing, then bisection.  No crossing: no saddle point.
+ *
+ * Then (Sec. II.A):
+ *   tunnel exit q0 = Re int_{t_s}^{t0} A dt (along z),
+ *   S_down^0 = I_p t_s - int_{t_s}^{t0} [k + A(t) - A(t0)]^2 / 2 dt,
+ * both integrals along the straight path t = t0 + i s, s from t_t to 0, by
+ * composite 16-point Gauss-Legendre quadrature on panels no wider than
+ * 0.5 a.u.; and the ionisation matrix element of Eq. (1)
+ *   m = <kappa_s| z E(t_s) |psi_0> / sqrt(E(t_s) kappa_z(t_s)),
+ * kappa_s = k + A(t_s) - A(t0) complex.  Reading: <kappa| is the plane wave
+ * (2 pi)^{-3/2} e^{i kappa.x} continued analytically in kappa (no complex
+ * conjugation of the complex part, as for real momenta), the square root is
+ * the principal one, and psi_0 is the GTO sum of the recombination element.
+ * For a primitive c e^{-a|x-Ra|^2} (times n.(x-Ra) for p) the Gaussian
+ * integral gives, with kappa^2 = kappa.kappa and
+ * G = c (2a)^{-3/2} e^{-kappa^2/(4a) - i kappa.Ra}:
+ *   s:  G (Ra_z - i kappa_z/(2a))
+ *   p:  G (-i Ra_z n.kappa/(2a) + n_z/(2a) - n.kappa kappa_z/(4a^2)). */
+int orc_sfa_step(const orc_problem* P, double t0, const double kperp[2], const double n[3],
+                 double out[7]) {
+  double E0r, A0r;
+  orc_field(P, t0, &E0r, &A0r);
+  for (int i = 0; i < 7; ++i) out[i] = 0.0;
+  if (E0r == 0.0) return -1;
+  double kp2 = kperp[0] * kperp[0] + kperp[1] * kperp[1];
+  double kap0 = sqrt(2.0 * P->Ip + kp2);
+  double sg = E0r > 0.0 ? 1.0 : -1.0;
+  /* h(s) = -sgn E(t0) Im A(t0 + i s) - kap0 starts at -kap0 < 0 */
+  double lo = 0.0, hi = -1.0;
+  for (int i = 1; i <= 150; ++i) {
+    double s = (double)i;
+    double h = -sg * cimag(vecpot_c(P, t0 + I * s)) - kap0;
+    if (h >= 0.0) {
+      hi = s;
+      break;
+    }
+    lo = s;
+  }
+  if (hi < 0.0) return -1;
+  for (int it = 0; it < 200; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    double h = -sg * cimag(vecpot_c(P, t0 + I * mid)) - kap0;
+    if (h >= 0.0) hi = mid;
+    else lo = mid;
+  }
+  double tt = 0.5 * (lo + hi);
+  double complex ts = t0 + I * tt;
+  double complex As = vecpot_c(P, ts);
+  double kz = A0r - creal(As);
+
+  /* integrals from t_s to t0 along t = t0 + i s: int_{t_s}^{t0} f dt =
+   * -i int_0^{t_t} f(t0 + i s) ds */
+  double gx[16], gw[16];
+  gauss_legendre16(gx, gw);
+  int panels = (int)ceil(tt / 0.5);
+  if (panels < 1) panels = 1;
+  double width = tt / panels;
+  double complex intA = 0.0, intK2 = 0.0;
+  for (int pnl = 0; pnl < panels; ++pnl) {
+    double a = pnl * width;
+    for (int j = 0; j < 16; ++j) {
+      double s = a + 0.5 * width * (gx[j] + 1.0);
+      double complex A = vecpot_c(P, t0 + I * s);
+      double complex kz_t = kz + A - A0r;
+      intA += 0.5 * width * gw[j] * A;
+      intK2 += 0.5 * width * gw[j] * (kp2 + kz_t * kz_t);
+    }
+  }
+  intA *= -I;
+  intK2 *= -I;
+  double q0z = creal(intA);
+  double complex S = P->Ip * ts - 0.5 * intK2;
+
+  /* matrix element and its denominator */
+  double complex Es = field_c(P, ts);
+  double complex kzs = kz + As - A0r;
+  double complex kap[3] = {kperp[0], kperp[1], kzs};
+  double complex k2 = kap[0] * kap[0] + kap[1] * kap[1] + kap[2] * kap[2];
+  double complex nk = n[0] * kap[0] + n[1] * kap[1] + n[2] * kap[2];
+  double complex me = 0.0;
+  for (int j = 0; j < P->n_gto; ++j) {
+    double a = P->gto_a[j];
+    double sgn = (P->gto_center[j] == 0) ? 1.0 : -1.0;
+    double Ra[3] = {sgn * 0.5 * P->R * n[0], sgn * 0.5 * P->R * n[1], sgn * 0.5 * P->R * n[2]};
+    double complex kR = kap[0] * Ra[0] + kap[1] * Ra[1] + kap[2] * Ra[2];
+    double complex G = P->gto_c[j] * pow(2.0 * a, -1.5) * cexp(-k2 / (4.0 * a) - I * kR);
+    if (P->gto_l[j] == 0)
+      me += G * (Ra[2] - I * kzs / (2.0 * a));
+    else
+      me += G * (-I * Ra[2] * nk / (2.0 * a) + n[2] / (2.0 * a) - nk * kzs / (4.0 * a * a));
+  }
+  me *= Es;
+  double complex m = me / csqrt(Es * kzs);
+  out[0] = tt;
+  out[1] = kz;
+  out[2] = q0z;
+  out[3] = creal(S);
+  out[4] = cimag(S);
+  out[5] = creal(m);
+  out[6] = cimag(m);
+  return 0;
+}
+
 /* ----------------------------------------------------------------- Philox */
 /* Philox4x32-10 (Salmon, Moraes, Dror and Shaw, "Parallel random numbers:
  * as easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplications
@@ -224,7 +397,8 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 static double unit_open(uint32_t x) { return ((double)x + 0.5) * (1.0 / 4294967296.0); }
 
 static void sample_one(const orc_problem* P, uint64_t seed, uint64_t j, int32_t N, double E0,
-                       int32_t* k0, double q0[3], double p0[3], double nax[3], double* w) {
+                       int32_t* k0, double q0[3], double p0[3], double nax[3], double* w,
+                       double* dph) {
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
   uint32_t c0[4] = {(uint32_t)j, (uint32_t)(j >> 32), 0u, 0u};
   uint32_t c1[4] = {(uint32_t)j, (uint32_t)(j >> 32), 0u, 1u};
@@ -258,24 +432,44 @@ static void sample_one(const orc_problem* P, uint64_t seed, uint64_t j, int32_t 
   double F = fabs(E);
   double ww = 0.0;
   q0[0] = q0[1] = q0[2] = 0.0;
-  if (F > 0.0) {
+  *dph = 0.0;
+  if (P->ionization == ORC_ION_SADDLE) {
+    /* Monte Carlo over the ionisation amplitude of Eq. (1): t0 uniform on
+     * the grid, k_perp from the Gaussian above, the axis from its density;
+     * weight |m e^{i S}| over the k_perp density, in units of the
+     * tunnelling factor e^{-kappa^3/(3 E0)} at the peak field (kappa^2 =
+     * 2 I_p), and the birth phase beyond I_p t0 + p0.q0 in dph. */
+    double t0 = orc_time(P, k), out[7];
+    if (orc_sfa_step(P, t0, p0, nax, out) == 0) {
+      double kap = sqrt(2.0 * P->Ip);
+      double kp2 = p0[0] * p0[0] + p0[1] * p0[1];
+      double complex m = out[5] + I * out[6];
+      p0[2] = out[1];
+      q0[2] = out[2];
+      ww = cabs(m) * exp(-out[4] + kap * kap * kap / (3.0 * E0) +
+                         kp2 / (2.0 * P->sigma_perp * P->sigma_perp));
+      *dph = (out[3] - P->Ip * t0) + carg(m);
+    }
+  } else if (F > 0.0) {
     double kap = sqrt(2.0 * P->Ip);
     ww = pow(E0 / F, 0.5 * (2.0 / kap - 1.0)) *
          exp(-(kap * kap * kap / 3.0) * (1.0 / F - 1.0 / E0));
     q0[2] = -(P->Ip + 0.5 * (p0[0] * p0[0] + p0[1] * p0[1] + p0[2] * p0[2])) / E;
   }
   if (!(ww >= P->w_cut)) ww = 0.0;
+  if (ww == 0.0) *dph = 0.0;
   *k0 = k;
   *w = ww;
 }
 
 void orc_sample(const orc_problem* P, uint64_t seed, uint64_t first, uint64_t n, int32_t* k0,
-                double* q0, double* p0, double* nax, double* w) {
+                double* q0, double* p0, double* nax, double* w, double* dph) {
   double E0;
   int32_t N;
   orc_laser(P, NULL, &E0, NULL, &N);
   for (uint64_t i = 0; i < n; ++i)
-    sample_one(P, seed, first + i, N, E0, &k0[i], &q0[3 * i], &p0[3 * i], &nax[3 * i], &w[i]);
+    sample_one(P, seed, first + i, N, E0, &k0[i], &q0[3 * i], &p0[3 * i], &nax[3 * i], &w[i],
+               &dph[i]);
 }
 
 /* ------------------------------------------------------------- propagation */
@@ -339,8 +533,8 @@ static void rk4_step(const orc_problem* P, const double n[3], int32_t k, double 
  * from the first step with |C_k| > c_max on, the trajectory contributes
  * nothing and is not propagated further. */
 static int traj_core(const orc_problem* P, int32_t k0, int32_t k_end, const double q0[3],
-                     const double p0[3], const double n[3], double w, double* amp_re,
-                     double* amp_im, double* c_re, double* c_im, double* accum,
+                     const double p0[3], const double n[3], double w, double dph,
+                     double* amp_re, double* amp_im, double* c_re, double* c_im, double* accum,
                      double* final_state) {
   int32_t N;
   orc_laser(P, NULL, NULL, NULL, &N);
@@ -365,7 +559,7 @@ static int traj_core(const orc_problem* P, int32_t k0, int32_t k_end, const doub
     if (c_re) c_re[k] = creal(C);
     if (c_im) c_im[k] = cimag(C);
     if (P->c_max > 0.0 && cabs(C) > P->c_max) break;
-    double phi = y[42] - P->Ip * (orc_time(P, k) - t0) + p0q0;
+    double phi = y[42] - P->Ip * (orc_time(P, k) - t0) + p0q0 + dph;
     double rre, rim;
     orc_recombination(P, n, y + 3, y, &rre, &rim);
     double complex a = -w * C * cexp(I * phi) * (rre + I * rim);
@@ -385,9 +579,11 @@ static int traj_core(const orc_problem* P, int32_t k0, int32_t k_end, const doub
 }
 
 int orc_trajectory(const orc_problem* P, int32_t k0, int32_t k_end, const double q0[3],
-                   const double p0[3], const double nax[3], double w, double* amp_re,
-                   double* amp_im, double* c_re, double* c_im, double* final_state) {
-  return traj_core(P, k0, k_end, q0, p0, nax, w, amp_re, amp_im, c_re, c_im, NULL, final_state);
+                   const double p0[3], const double nax[3], double w, double dph,
+                   double* amp_re, double* amp_im, double* c_re, double* c_im,
+                   double* final_state) {
+  return traj_core(P, k0, k_end, q0, p0, nax, w, dph, amp_re, amp_im, c_re, c_im, NULL,
+                   final_state);
 }
 
 /* ------------------------------------------------------------ the ensemble */
@@ -410,10 +606,10 @@ static void* run_range(void* arg) {
   orc_laser(J->P, NULL, &E0, NULL, &N);
   for (uint64_t i = 0; i < J->n; ++i) {
     int32_t k0;
-    double q0[3], p0[3], nax[3], w;
-    sample_one(J->P, J->seed, J->first + i, N, E0, &k0, q0, p0, nax, &w);
+    double q0[3], p0[3], nax[3], w, dph;
+    sample_one(J->P, J->seed, J->first + i, N, E0, &k0, q0, p0, nax, &w, &dph);
     if (w == 0.0) continue;
-    traj_core(J->P, k0, N, q0, p0, nax, w, NULL, NULL, NULL, NULL, J->accum, NULL);
+    traj_core(J->P, k0, N, q0, p0, nax, w, dph, NULL, NULL, NULL, NULL, J->accum, NULL);
     J->live_steps += (uint64_t)(N - k0);
     J->n_live += 1;
   }

@@ -33,6 +33,9 @@ enum {
 };
 
 enum { ORC_ALIGN_FIXED = 0, ORC_ALIGN_COS2M = 1 };
+/* ionisation step: first-order tunnel exit with an ADK-like weight, or the
+ * complex saddle point of Eq. (2) with the matrix element of Eq. (1) */
+enum { ORC_ION_FIRST_ORDER = 0, ORC_ION_SADDLE = 1 };
 
 typedef struct {
   /* laser: linear polarisation along z, sin^2 envelope */
@@ -54,6 +57,7 @@ typedef struct {
   double dt, gamma, w_cut, sigma_perp;
   int32_t n_steps; /* 0 = round(tau / dt) */
   double c_max;    /* > 0: a trajectory stops contributing once |C| > c_max */
+  int32_t ionization; /* ORC_ION_FIRST_ORDER or ORC_ION_SADDLE */
 } orc_problem;
 
 /* laser constants: omega, peak field E0, pulse length tau, steps N */
@@ -70,18 +74,31 @@ void orc_recombination(const orc_problem* P, const double n[3], const double p[3
                        const double q[3], double* re, double* im);
 /* det of the HK matrix R built from a 6x6 monodromy matrix (row-major) */
 void orc_prefactor_det(const double M[36], double gamma, double* re, double* im);
+/* exact SFA ionisation step for birth time t0, transverse momentum kperp and
+ * axis n: out = {t_t, k_z, q0_z, Re S, Im S, Re m, Im m} with t_s = t0 + i t_t
+ * the saddle point, S the tunnelling action S_down^0, q0_z the tunnel exit
+ * and m = <kappa|z E(t_s)|psi_0> / sqrt(E(t_s) kappa_z).  Returns 0, or -1
+ * when no saddle point exists (the trajectory is not born). */
+int orc_sfa_step(const orc_problem* P, double t0, const double kperp[2], const double n[3],
+                 double out[7]);
+/* the laser continued to complex time t = tr + i ti: A(t) and E(t) */
+void orc_field_complex(const orc_problem* P, double tr, double ti, double* A_re, double* A_im,
+                       double* E_re, double* E_im);
 /* Philox4x32-10 block function */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
-/* sample trajectories first..first+n-1 of a problem with a given seed */
+/* sample trajectories first..first+n-1 of a problem with a given seed; dph
+ * receives each trajectory's birth phase beyond I_p t0 + p0.q0 (0 for the
+ * first-order step) */
 void orc_sample(const orc_problem* P, uint64_t seed, uint64_t first, uint64_t n, int32_t* k0,
-                double* q0, double* p0, double* nax, double* w);
+                double* q0, double* p0, double* nax, double* w, double* dph);
 /* propagate one trajectory from step k0 to step k_end (<= N).  amp_re/amp_im
  * (nullable, length N+1) receive a_k for k0 <= k <= k_end; c_re/c_im
  * (nullable, length N+1) the HK prefactor C_k; final (nullable) receives
  * ORC_NFINAL doubles at the last step reached.  Returns 0, or -1 on bad input. */
 int orc_trajectory(const orc_problem* P, int32_t k0, int32_t k_end, const double q0[3],
-                   const double p0[3], const double nax[3], double w, double* amp_re,
-                   double* amp_im, double* c_re, double* c_im, double* final_state);
+                   const double p0[3], const double nax[3], double w, double dph,
+                   double* amp_re, double* amp_im, double* c_re, double* c_im,
+                   double* final_state);
 /* whole estimator: sample trajectories first..first+n-1, propagate the live
  * ones, accum[k] = sum_j Re a_jk (length N+1).  Returns 0 or -1. */
 int orc_run(const orc_problem* P, uint64_t seed, uint64_t first, uint64_t n, int32_t nthreads,
