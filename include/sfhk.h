@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define SFHK_ABI_VERSION 1
+#define SFHK_ABI_VERSION 2
 #define SFHK_MAX_GTO 64
 #define SFHK_MAX_PROBLEMS 65535
 
@@ -49,6 +49,15 @@ typedef enum {
 
 typedef enum { SFHK_FP64 = 0, SFHK_MIXED = 1 } sfhk_precision;
 typedef enum { SFHK_ALIGN_FIXED = 0, SFHK_ALIGN_COS2M = 1 } sfhk_align_kind;
+
+/* Ionisation step of sfhk_sample_initial.  FIRST_ORDER: birth at the tunnel
+ * exit of Eq. 2 expanded to first order about t0, p0 = (k_perp, 0), weight
+ * from the quasi-static tunnelling rate.  SADDLE: the complex saddle point of
+ * Eq. 2 for real momentum (t_s = t0 + i t_t, k_z fixed by Eq. 2), tunnel exit
+ * Re int A, and the amplitude of Eq. 1 (matrix element of r.E(t_s) over
+ * sqrt(E.kappa), times e^{i(S_down^0 + p0.q0)}) split into the weight w (its
+ * modulus over the k_perp proposal density) and the birth phase dph. */
+typedef enum { SFHK_ION_FIRST_ORDER = 0, SFHK_ION_SADDLE = 1 } sfhk_ionization;
 
 /* One centre of the two-centre model potential (Eq. 7, Table I):
  * V_i = -[Zinf + dZ exp(-alpha rho)] / rho, rho = sqrt(|r - R_i|^2 + eps2).
@@ -102,7 +111,7 @@ typedef struct {
   double w_cut;      /* trajectories with weight below it are not propagated */
   double sigma_perp; /* std. dev. of each transverse initial momentum       */
   int32_t n_steps;   /* 0: N = round(tau / dt); time grid t_k = -tau/2 + k dt */
-  int32_t reserved;
+  int32_t ionization; /* sfhk_ionization: how sfhk_sample_initial draws the birth */
   double c_max;      /* optional prefactor cap: > 0 stops a trajectory's contributions from
                         the first step with |C| > c_max (a filter of chaotic trajectories
                         the paper does not use); <= 0: prefactor fully included */
@@ -113,7 +122,8 @@ typedef struct {
  * sum of n_per_prob.  Filled by sfhk_sample_initial:
  *   k0    birth step (int32), prob problem index (int32),
  *   q0 = (qx,qy,qz), p0 = (px,py,pz), weight w (0 = not propagated),
- *   axis n = (nx,ny,nz);
+ *   axis n = (nx,ny,nz), birth phase dph (the phase of the trajectory's
+ *   ionisation amplitude beyond I_p t0 + p0.q0; 0 for the first-order step);
  *   order[capacity]: slot ids of the live trajectories sorted by (problem,
  *       k0), ties by slot id; entries past the live total are unspecified;
  *   live_start[n_prob], live_count[n_prob]: each problem's run in `order`;
@@ -127,6 +137,7 @@ typedef struct {
   double *px, *py, *pz;
   double* w;
   double *nx, *ny, *nz;
+  double* dph;
   uint32_t* order;
   uint32_t* live_start;
   uint32_t* live_count;

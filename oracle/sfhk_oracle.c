@@ -235,7 +235,8 @@ static void gauss_legendre16(double x[16], double wt[16]) {
  *   k_z = A(t0) - Re A(t0 + i t_t)                           (fixes k_z).
  * Reading: the root with the smallest t_t > 0 (the saddle point closest to
  * the real axis), found by stepping t_t by 1 a.u. from 0 up to 150 a.u. to
- * the first crossing, then bisection.  No crossing: no saddle point.
+ * the first crossing, then bisection.  No crossing, or a vanishing field at
+ * t0: no saddle point.
  *
  * Then (Sec. II.A):
  *   tunnel exit q0 = Re int_{t_s}^{t0} A dt (along z),
@@ -255,10 +256,14 @@ static void gauss_legendre16(double x[16], double wt[16]) {
  *   p:  G (-i Ra_z n.kappa/(2a) + n_z/(2a) - n.kappa kappa_z/(4a^2)). */
 int orc_sfa_step(const orc_problem* P, double t0, const double kperp[2], const double n[3],
                  double out[7]) {
-  double E0r, A0r;
+  double E0r, A0r, Epk;
   orc_field(P, t0, &E0r, &A0r);
+  orc_laser(P, NULL, &Epk, NULL, NULL);
   for (int i = 0; i < 7; ++i) out[i] = 0.0;
-  if (E0r == 0.0) return -1;
+  /* Reading: no birth where the field vanishes (|E(t0)| <= 1e-12 E0, e.g. at
+   * the pulse ends, where E = 0 exactly and rounding would pick the sign that
+   * selects the saddle point) */
+  if (!(fabs(E0r) > 1e-12 * Epk)) return -1;
   double kp2 = kperp[0] * kperp[0] + kperp[1] * kperp[1];
   double kap0 = sqrt(2.0 * P->Ip + kp2);
   double sg = E0r > 0.0 ? 1.0 : -1.0;
@@ -446,8 +451,9 @@ static void sample_one(const orc_problem* P, uint64_t seed, uint64_t j, int32_t 
       double complex m = out[5] + I * out[6];
       p0[2] = out[1];
       q0[2] = out[2];
-      ww = cabs(m) * exp(-out[4] + kap * kap * kap / (3.0 * E0) +
-                         kp2 / (2.0 * P->sigma_perp * P->sigma_perp));
+      /* sigma_perp = 0: k_perp = 0, no proposal density to divide out */
+      double comp = P->sigma_perp > 0.0 ? kp2 / (2.0 * P->sigma_perp * P->sigma_perp) : 0.0;
+      ww = cabs(m) * exp(-out[4] + kap * kap * kap / (3.0 * E0) + comp);
       *dph = (out[3] - P->Ip * t0) + carg(m);
     }
   } else if (F > 0.0) {

@@ -60,7 +60,7 @@ class Ensemble:
     """Device structure of arrays of a sampled ensemble (see sfhk_ensemble)."""
 
     FIELDS_I32 = ("k0", "prob")
-    FIELDS_F64 = ("qx", "qy", "qz", "px", "py", "pz", "w", "nx", "ny", "nz")
+    FIELDS_F64 = ("qx", "qy", "qz", "px", "py", "pz", "w", "nx", "ny", "nz", "dph")
 
     def __init__(self, capacity, n_prob, device="cuda"):
         cap = max(int(capacity), 1)

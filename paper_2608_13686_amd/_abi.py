@@ -47,7 +47,7 @@ class Align(C.Structure):
 class Problem(C.Structure):
     _fields_ = [("tgt", Target), ("las", Laser), ("al", Align), ("dt", C.c_double),
                 ("gamma_cs", C.c_double), ("w_cut", C.c_double), ("sigma_perp", C.c_double),
-                ("n_steps", C.c_int32), ("reserved", C.c_int32), ("c_max", C.c_double)]
+                ("n_steps", C.c_int32), ("ionization", C.c_int32), ("c_max", C.c_double)]
 
 
 class Ensemble(C.Structure):
@@ -55,8 +55,11 @@ class Ensemble(C.Structure):
                 ("qx", C.c_void_p), ("qy", C.c_void_p), ("qz", C.c_void_p),
                 ("px", C.c_void_p), ("py", C.c_void_p), ("pz", C.c_void_p),
                 ("w", C.c_void_p), ("nx", C.c_void_p), ("ny", C.c_void_p), ("nz", C.c_void_p),
-                ("order", C.c_void_p), ("live_start", C.c_void_p), ("live_count", C.c_void_p),
+                ("dph", C.c_void_p), ("order", C.c_void_p), ("live_start", C.c_void_p), ("live_count", C.c_void_p),
                 ("pack_start", C.c_void_p)]
+
+
+IONIZATION = {"first_order": 0, "saddle": 1}
 
 
 class Tuning(C.Structure):
@@ -167,6 +170,7 @@ def make_problems(dicts):
         P.sigma_perp = d["sigma_perp"]
         P.n_steps = int(d.get("n_steps", 0))
         P.c_max = float(d.get("c_max", 0.0))
+        P.ionization = IONIZATION[d.get("ionization", "first_order")]
     arr._keep = keep
     return arr
 

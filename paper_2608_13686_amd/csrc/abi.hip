@@ -70,6 +70,12 @@ sfhk_status check_problem(const sfhk_problem* p, int idx) {
     return fail(SFHK_E_INVALID, "problem %d: sigma_perp must be >= 0", idx);
   if (!is_finite(p->c_max)) return fail(SFHK_E_INVALID, "problem %d: c_max not finite", idx);
   if (p->n_steps < 0) return fail(SFHK_E_INVALID, "problem %d: n_steps must be >= 0", idx);
+  if (p->ionization != SFHK_ION_FIRST_ORDER && p->ionization != SFHK_ION_SADDLE)
+    return fail(SFHK_E_INVALID, "problem %d: unknown ionisation step %d", idx, p->ionization);
+  // the saddle-point step writes the pulse as carriers w and w +- 2 pi/tau;
+  // one cycle makes w - 2 pi/tau vanish
+  if (p->ionization == SFHK_ION_SADDLE && !(p->las.n_cycles > 1.0))
+    return fail(SFHK_E_INVALID, "problem %d: the saddle-point step needs n_cycles > 1", idx);
   const sfhk_target& T = p->tgt;
   if (!(is_finite(T.R) && T.R >= 0)) return fail(SFHK_E_INVALID, "problem %d: R must be >= 0", idx);
   if (!(is_finite(T.Ip) && T.Ip > 0)) return fail(SFHK_E_INVALID, "problem %d: Ip must be > 0", idx);
@@ -133,6 +139,7 @@ Desc make_desc(const sfhk_problem& p) {
   d.align_m = p.al.m;
   d.n_gto = p.tgt.n_gto;
   d.screened = (p.tgt.ctr[0].dZ != 0.0 || p.tgt.ctr[1].dZ != 0.0) ? 1 : 0;
+  d.ionization = p.ionization;
   d.half_R = 0.5 * p.tgt.R;
   d.Ip = p.tgt.Ip;
   d.gamma = p.gamma_cs;
@@ -164,8 +171,8 @@ Desc make_desc(const sfhk_problem& p) {
   for (int j = 0; j < p.tgt.n_gto; ++j) {
     const sfhk_gto& G = p.tgt.gto[j];
     const double k2 = 1.0 / (4.0 * G.a) + 1.0 / (2.0 * g);
-    d.g_sgn[j] = G.center == 0 ? 1.0 : -1.0;
-    d.g_l[j] = G.l;
+    d.g_l[j] = G.l | (G.center << 1);
+    d.g_ion[j] = G.c * std::pow(2.0 * G.a, -1.5);
     d.g_inv4k[j] = 1.0 / (4.0 * k2);
     d.g_inv2k[j] = 1.0 / (2.0 * k2);
     d.g_norm[j] = G.c * std::pow(2.0 * G.a, -1.5) * std::pow(kPi * g, -0.75) *
@@ -258,7 +265,7 @@ sfhk_status check_ensemble(const sfhk_ensemble* e) {
     return fail(SFHK_E_INVALID, "ensemble capacity must be < 2^32");
   if (e->capacity == 0) return SFHK_OK;
   const void* ptrs[] = {e->k0, e->prob, e->qx, e->qy, e->qz, e->px, e->py, e->pz,
-                        e->w, e->nx, e->ny, e->nz, e->order, e->live_start,
+                        e->w, e->nx, e->ny, e->nz, e->dph, e->order, e->live_start,
                         e->live_count, e->pack_start};
   for (const void* q : ptrs)
     if (!q) return fail(SFHK_E_INVALID, "ensemble has a null device array");
@@ -279,6 +286,7 @@ EnsPtrs ens_ptrs(const sfhk_ensemble* e) {
   p.nx = e->nx;
   p.ny = e->ny;
   p.nz = e->nz;
+  p.dph = e->dph;
   p.order = e->order;
   p.live_start = e->live_start;
   p.live_count = e->live_count;

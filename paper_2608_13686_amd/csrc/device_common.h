@@ -274,7 +274,7 @@ __device__ __forceinline__ double amplitude_re(const Desc& d, const double n[3],
   const double bb_re_p = pp * d.inv_gamma2;
   double rr = 0.0, ri = 0.0;
   for (int j = 0; j < d.n_gto; ++j) {
-    const int c = d.g_sgn[j] > 0.0 ? 0 : 1;
+    const int c = (d.g_l[j] >> 1) & 1;
     const double ddc = c == 0 ? dd[0] : dd[1];
     const double pdc = c == 0 ? pd[0] : pd[1];
     const double dzc = c == 0 ? dz[0] : dz[1];
@@ -287,7 +287,7 @@ __device__ __forceinline__ double amplitude_re(const Desc& d, const double n[3],
     sincos(ei, &sn, &cs);
     const double Gr = gm * cs, Gi = gm * sn;
     double Xr, Xi;
-    if (d.g_l[j] == 0) {
+    if ((d.g_l[j] & 1) == 0) {
       Xr = bzr * i2;
       Xi = dzc * i2;
     } else {

@@ -39,7 +39,8 @@ __device__ __forceinline__ void run_pack(const Desc* __restrict__ descs,
   const double n[3] = {e.nx[slot], e.ny[slot], e.nz[slot]};
   const double w = e.w[slot];
   const double t0 = d.t_first + (double)k0 * d.dt;
-  const double p0q0 = p[0] * q[0] + p[1] * q[1] + p[2] * q[2];
+  // phase constant of the amplitude: p0.q0 plus the birth phase
+  const double p0q0 = p[0] * q[0] + p[1] * q[1] + p[2] * q[2] + e.dph[slot];
   double S = 0.0;
 #pragma unroll
   for (int i = 0; i < kMonoElems; ++i) mono[i][lane] = (i % 7 == 0) ? 1.0 : 0.0;

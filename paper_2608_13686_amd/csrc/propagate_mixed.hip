@@ -29,7 +29,7 @@ __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
   const double n[3] = {e.nx[slot], e.ny[slot], e.nz[slot]};
   const double w = e.w[slot];
   const double t0 = d.t_first + (double)k0 * d.dt;
-  const double p0q0 = p0d[0] * q0d[0] + p0d[1] * q0d[1] + p0d[2] * q0d[2];
+  const double p0q0 = p0d[0] * q0d[0] + p0d[1] * q0d[1] + p0d[2] * q0d[2] + e.dph[slot];
   float q[3] = {(float)q0d[0], (float)q0d[1], (float)q0d[2]};
   float p[3] = {(float)p0d[0], (float)p0d[1], (float)p0d[2]};
   const float hRn[3] = {(float)(d.half_R * n[0]), (float)(d.half_R * n[1]),

@@ -74,7 +74,8 @@ serve_slice_f64(const ReqDev* __restrict__ reqs, SliceTable tab) {
     flips = sv[SFHK_FS_FLIPS * st];
     kend = (int)sv[kStateKend * st];
   }
-  const double p0q0 = R.px[slot] * R.qx[slot] + R.py[slot] * R.qy[slot] + R.pz[slot] * R.qz[slot];
+  const double p0q0 =
+      R.px[slot] * R.qx[slot] + R.py[slot] * R.qy[slot] + R.pz[slot] * R.qz[slot] + R.dph[slot];
   double Rr[3][3], Ri[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)

@@ -25,7 +25,7 @@ namespace {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct ReqLayout {
-  size_t field, accum, v, vre, vim, yield, k0, prob, f64[10], order, runs, hist, cursor, state,
+  size_t field, accum, v, vre, vim, yield, k0, prob, f64[11], order, runs, hist, cursor, state,
       slot_off, bytes;
 };
 
@@ -45,7 +45,7 @@ ReqLayout req_layout(int64_t N, uint64_t n, int32_t n_omega) {
   L.yield = take(sizeof(double) * (size_t)n_omega);
   L.k0 = take(sizeof(int32_t) * n);
   L.prob = take(sizeof(int32_t) * n);
-  for (int i = 0; i < 10; ++i) L.f64[i] = take(sizeof(double) * n);
+  for (int i = 0; i < 11; ++i) L.f64[i] = take(sizeof(double) * n);
   L.order = take(sizeof(uint32_t) * n);
   L.runs = take(sizeof(uint32_t) * 4);
   L.hist = take(sizeof(uint32_t) * (size_t)(N + 2));
@@ -120,8 +120,9 @@ sfhk_status sfhk_request_init(const sfhk_problem* p, uint64_t n_traj, uint64_t s
   r.yield = reinterpret_cast<double*>(b + L.yield);
   r.k0 = reinterpret_cast<int32_t*>(b + L.k0);
   r.prob = reinterpret_cast<int32_t*>(b + L.prob);
-  double** f64[10] = {&r.qx, &r.qy, &r.qz, &r.px, &r.py, &r.pz, &r.w, &r.nx, &r.ny, &r.nz};
-  for (int i = 0; i < 10; ++i) *f64[i] = reinterpret_cast<double*>(b + L.f64[i]);
+  double** f64[11] = {&r.qx, &r.qy, &r.qz, &r.px, &r.py, &r.pz, &r.w,
+                      &r.nx, &r.ny, &r.nz, &r.dph};
+  for (int i = 0; i < 11; ++i) *f64[i] = reinterpret_cast<double*>(b + L.f64[i]);
   r.order = reinterpret_cast<uint32_t*>(b + L.order);
   uint32_t* runs = reinterpret_cast<uint32_t*>(b + L.runs);
   r.live_start = runs;
@@ -137,7 +138,7 @@ sfhk_status sfhk_request_init(const sfhk_problem* p, uint64_t n_traj, uint64_t s
   uint32_t* cursor = reinterpret_cast<uint32_t*>(b + L.cursor);
   uint64_t* slot_off = reinterpret_cast<uint64_t*>(b + L.slot_off);
   EnsPtrs ep{r.k0, r.prob, r.qx, r.qy, r.qz, r.px, r.py, r.pz, r.w, r.nx, r.ny, r.nz,
-             r.order, r.live_start, r.live_count, r.pack_start};
+             r.dph, r.order, r.live_start, r.live_count, r.pack_start};
   const Desc* ddev = &dst->desc;
   hipError_t e = launch_write_req(r, dst, s);
   if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t*>(slot_off), 0u, 4, s);

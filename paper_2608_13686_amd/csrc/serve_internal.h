@@ -17,7 +17,7 @@ struct ReqDev {
   const double* field;
   double *accum, *v, *V_re, *V_im, *yield;
   int32_t *k0, *prob;
-  double *qx, *qy, *qz, *px, *py, *pz, *w, *nx, *ny, *nz;
+  double *qx, *qy, *qz, *px, *py, *pz, *w, *nx, *ny, *nz, *dph;
   uint32_t *order, *live_start, *live_count, *pack_start;
   double* state;     // [kStateFields][live_cap], indexed by pack position
   uint64_t live_cap;

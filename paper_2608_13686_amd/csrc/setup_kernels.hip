@@ -1,5 +1,6 @@
 // Field table, initial-condition sampling, counting sort into 64-lane packs,
 // dipole normalisation and the windowed Fourier transform.
+#include "sfa_step.h"
 #include "sfhk_internal.h"
 
 namespace sfhk {
@@ -110,12 +111,24 @@ __global__ void sample_kernel(const Desc* __restrict__ descs, int n_prob,
 
   double E = field[d.field_off + 2 * (uint64_t)k0];
   double F = fabs(E);
-  double w = 0.0, qz = 0.0;
-  if (F > 0.0) {
+  double w = 0.0, qz = 0.0, pz = 0.0, dph = 0.0;
+  if (d.ionization == SFHK_ION_SADDLE) {
+    const double nn[3] = {nx, ny, nz};
+    SfaBirth b;
+    if (sfa_birth(d, d.t_first + (double)k0 * d.dt, px, py, nn, b)) {
+      w = b.w;
+      qz = b.q0z;
+      pz = b.kz;
+      dph = b.dph;
+    }
+  } else if (F > 0.0) {
     w = pow(d.E0 / F, d.wpow) * exp(-d.kcube3 * (1.0 / F - d.inv_E0));
     qz = -(d.Ip + 0.5 * (px * px + py * py)) / E;
   }
-  if (!(w >= d.w_cut)) w = 0.0;
+  if (!(w >= d.w_cut)) {
+    w = 0.0;
+    dph = 0.0;
+  }
 
   e.k0[i] = k0;
   e.prob[i] = P;
@@ -124,7 +137,8 @@ __global__ void sample_kernel(const Desc* __restrict__ descs, int n_prob,
   e.qz[i] = qz;
   e.px[i] = px;
   e.py[i] = py;
-  e.pz[i] = 0.0;
+  e.pz[i] = pz;
+  e.dph[i] = dph;
   e.w[i] = w;
   e.nx[i] = nx;
   e.ny[i] = ny;

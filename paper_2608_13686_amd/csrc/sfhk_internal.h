@@ -18,7 +18,7 @@ struct Desc {
   // laser and time grid (Sec. II.D pulse, grid t_k = t_first + k dt)
   double omega, E0, tau, cep, dt, t_first;
   int32_t N, align_kind, align_m, n_gto;
-  int32_t screened, pad0;
+  int32_t screened, ionization;
   // target (Eq. 7) and coherent state
   double half_R, Ip, gamma, inv_gamma, inv_gamma2, half_inv_gamma;
   double Zinf[2], dZ[2], alpha[2], eps2[2];
@@ -31,9 +31,10 @@ struct Desc {
   uint64_t field_off;  // doubles: E(t_k) at 2k, E(t_k + dt/2) at 2k + 1
   uint64_t acc_off;    // accum / histogram bin of step 0
   uint64_t slot_off, n_slots;
-  // GTO primitives: centre sign, l, 1/(4 kappa2), 1/(2 kappa2), normalisation,
-  // 1/(2a), with kappa2 = 1/(4a) + 1/(2 gamma)
-  double g_sgn[SFHK_MAX_GTO], g_inv4k[SFHK_MAX_GTO], g_inv2k[SFHK_MAX_GTO];
+  // GTO primitives: l | centre << 1 (centre 0 at +R/2 n), 1/(4 kappa2),
+  // 1/(2 kappa2), the recombination normalisation, 1/(2a) and c (2a)^{-3/2},
+  // with kappa2 = 1/(4a) + 1/(2 gamma)
+  double g_ion[SFHK_MAX_GTO], g_inv4k[SFHK_MAX_GTO], g_inv2k[SFHK_MAX_GTO];
   double g_norm[SFHK_MAX_GTO], g_i2a[SFHK_MAX_GTO];
   int32_t g_l[SFHK_MAX_GTO];
   double g_inv4k_min;  // smallest 1/(4 kappa2) over the primitives
@@ -44,7 +45,7 @@ struct Desc {
 struct EnsPtrs {
   int32_t* k0;
   int32_t* prob;
-  double *qx, *qy, *qz, *px, *py, *pz, *w, *nx, *ny, *nz;
+  double *qx, *qy, *qz, *px, *py, *pz, *w, *nx, *ny, *nz, *dph;
   uint32_t *order, *live_start, *live_count, *pack_start;
 };
 

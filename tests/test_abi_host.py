@@ -40,7 +40,20 @@ def test_library_exports_every_header_symbol(L):
 
 
 def test_abi_version(L):
-    assert L.lib().sfhk_abi_version() == 1
+    assert L.lib().sfhk_abi_version() == 2
+
+
+def test_ionisation_step_validated(L):
+    import ctypes as C
+    p = workloads.with_changes(workloads.n2(), ionization="saddle")
+    arr = L.make_problems([p])
+    n, t0, tau = C.c_int32(), C.c_double(), C.c_double()
+    assert L.lib().sfhk_problem_steps(arr, C.byref(n), C.byref(t0), C.byref(tau)) == 0
+    arr[0].ionization = 7
+    assert L.lib().sfhk_problem_steps(arr, C.byref(n), C.byref(t0), C.byref(tau)) == 1
+    one = L.make_problems([workloads.with_changes(p, **{"laser.n_cycles": 1.0})])
+    assert L.lib().sfhk_problem_steps(one, C.byref(n), C.byref(t0), C.byref(tau)) == 1
+    assert b"n_cycles > 1" in L.lib().sfhk_last_error()
 
 
 def test_problem_steps_matches_grid(L, orc):
@@ -126,9 +139,13 @@ def test_capacity_and_workspace_size_errors(L):
     p = _abi.make_problems([workloads.h2_softcore()])
     ens = _abi.Ensemble()
     ens.capacity = 8
+    n = _abi.u64_array([8])
     for f in ("k0", "prob", "qx", "qy", "qz", "px", "py", "pz", "w", "nx", "ny", "nz", "order",
               "live_start", "live_count", "pack_start"):
         setattr(ens, f, 64)  # never dereferenced: the call fails before enqueueing
+    assert lib.sfhk_sample_initial(p, 1, n, n, n, C.byref(ens), C.c_void_p(64), 1 << 40,
+                                   None) == 1  # the birth-phase array is missing
+    ens.dph = 64
     n = _abi.u64_array([9])
     assert lib.sfhk_sample_initial(p, 1, n, n, n, C.byref(ens), C.c_void_p(64), 1 << 40,
                                    None) == 2

@@ -1,0 +1,143 @@
+"""The exact SFA ionisation step on the GPU (Sec. II.A, Eq. 1-2) against the
+oracle: sampled births (birth step bit-exact; weight, momentum, exit and
+birth phase to rounding), dipoles through the step-wise path, plans and the
+serving loop.  Tolerance: relative L2 of the dipole <= 1e-10."""
+import cmath
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def sf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2608_13686_amd as sf
+    return sf
+
+
+def saddle(p):
+    return W.with_changes(p, ionization="saddle")
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    r = float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    print(f"relative L2 {r:.3e}", flush=True)
+    return r
+
+
+CASES = {
+    "h2": ([saddle(W.h2_softcore())], [3000], [1001]),
+    "n2pair": ([saddle(W.n2(0.0)), saddle(W.n2(90.0))], [3000, 3000], [1002, 1002]),
+    "cos4": ([saddle(W.n2(align=W.cos2m(2))),
+              saddle(W.h2_softcore(align=W.cos2m(2), laser=dict(W.H2_LASER, cep=1.0)))],
+             [2500, 1500], [77, 78]),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_saddle_sampling_matches_oracle(sf, orc, case):
+    import torch
+    probs, n, seeds = CASES[case]
+    ens, _ = sf.sample_initial(probs, n, seeds)
+    torch.cuda.synchronize()
+    g = {f: getattr(ens, f).cpu().numpy() for f in ens.FIELDS_I32 + ens.FIELDS_F64}
+    off = 0
+    for p, nn, sd in zip(probs, n, seeds):
+        o = orc.sample(p, sd, 0, nn)
+        sl = slice(off, off + nn)
+        off += nn
+        assert np.array_equal(g["k0"][sl], o["k0"])
+        live_g, live_o = g["w"][sl] > 0, o["w"] > 0
+        assert np.array_equal(live_g, live_o)
+        lw = live_o
+        assert lw.sum() > nn // 5
+        w_err = np.max(np.abs(g["w"][sl][lw] / o["w"][lw] - 1))
+        pz_err = np.max(np.abs(g["pz"][sl][lw] - o["p0"][lw, 2]))
+        qz_err = np.max(np.abs(g["qz"][sl][lw] - o["q0"][lw, 2]) / np.maximum(1, np.abs(o["q0"][lw, 2])))
+        ph_err = np.max(np.abs(np.exp(1j * g["dph"][sl][lw]) - np.exp(1j * o["dph"][lw])))
+        print(f"{p['name']}: {lw.sum()} live, max rel w {w_err:.2e}, p_z {pz_err:.2e}, "
+              f"q_z {qz_err:.2e}, e^(i dph) {ph_err:.2e}", flush=True)
+        assert w_err < 1e-10 and pz_err < 1e-11 and qz_err < 1e-11 and ph_err < 1e-10
+        assert np.all(g["dph"][sl][~live_g] == 0)
+        for f, col in (("px", 0), ("py", 1)):  # Box-Muller: last-bit differences of sin/cos
+            assert np.max(np.abs(g[f][sl] - o["p0"][:, col])) < 1e-14
+
+
+@pytest.mark.parametrize("case", ["h2", "cos4"])
+def test_saddle_dipole_matches_oracle(sf, orc, case):
+    import torch
+    probs, n, seeds = CASES[case]
+    out = sf.run(probs, n, seeds, h_max=30.0)
+    torch.cuda.synchronize()
+    for i, (p, nn, sd) in enumerate(zip(probs, n, seeds)):
+        vo, _, _ = orc.dipole(p, sd, 0, nn, NTHREADS)
+        print(p["name"], flush=True)
+        assert rel(out["v"][i].cpu().numpy(), vo) < 1e-10
+
+
+def test_saddle_final_states_match_oracle(sf, orc):
+    """Per-trajectory final states from the GPU's initial conditions and
+    birth phases, against the oracle propagating the oracle's own births."""
+    import torch
+    p = saddle(W.h2_softcore(30.0))
+    n, seed = 512, 4
+    ens, ws = sf.sample_initial([p], [n], [seed])
+    acc, fs = sf.propagate([p], ens, final_state=True, workspace=ws)
+    torch.cuda.synchronize()
+    fs = fs.cpu().numpy()
+    o = orc.sample(p, seed, 0, n)
+    live = np.nonzero(o["w"] > 0)[0]
+    assert len(live) > 50
+    for i in live[:40]:
+        a, fin = orc.trajectory(p, int(o["k0"][i]), o["q0"][i], o["p0"][i], o["nax"][i],
+                                o["w"][i], dph=o["dph"][i])
+        scale = max(1.0, np.abs(fin[6:42]).max())
+        assert np.max(np.abs(fs[:42, i] - fin[:42])) < 1e-9 * scale
+
+
+def test_saddle_plan_and_served_equal_stepwise(sf):
+    import torch
+    from paper_2608_13686_amd.serve import HipExecutor, Server
+    probs, n, seeds = CASES["cos4"]
+    ref = sf.run(probs, n, seeds, h_max=30.0, h_step=0.1)
+    torch.cuda.synchronize()
+    plan = sf.Plan(probs, n, seeds, tuning=(1, 8, 1, 1), h_max=30.0, h_step=0.1)
+    plan.run()
+    torch.cuda.synchronize()
+    x = HipExecutor(1 << 28, 4, 301, 0.1)
+    S = Server(x, 1 << 28, max_requests=4, window=700)
+    for i, (p, nn, sd) in enumerate(zip(probs, n, seeds)):
+        S.submit(i, p, nn, sd)
+    S.drain()
+    served = {r.tag: r.result for r in S.completed}
+    for i in range(len(probs)):
+        v = ref["v"][i].cpu().numpy()
+        assert rel(plan.v_of(i).cpu().numpy(), v) < 1e-12
+        assert rel(served[i]["v"].numpy(), v) < 1e-12
+    plan.close()
+
+
+def test_saddle_mixed_precision_error(sf):
+    """The FP32 stepping on saddle-point births, against FP64 on the same
+    births, with chaotic trajectories filtered by the prefactor cap."""
+    import torch
+    probs = [dict(saddle(W.h2_softcore()), c_max=1e3), dict(saddle(W.n2(0.0)), c_max=1e3)]
+    n, seeds = [20000, 20000], [1001, 1002]
+    out = {}
+    for prec in ("fp64", "mixed"):
+        ens, ws = sf.sample_initial(probs, n, seeds)
+        acc, _ = sf.propagate(probs, ens, precision=prec, workspace=ws)
+        torch.cuda.synchronize()
+        out[prec] = acc.cpu().numpy()
+    assert rel(out["mixed"], out["fp64"]) < 2e-3
