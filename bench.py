@@ -139,6 +139,57 @@ def timed_plan(sf, probs, n_traj, seeds, precision, tuning, steps, warmup, h_max
     return plan, el / steps
 
 
+def saddle_variant(sf, n_traj, steps, warmup):
+    """The headline N2 workload with births from the exact SFA saddle point:
+    whole step (sampling + propagation + dipole + spectra) and the sampler's
+    own time, both from HIP events on the stream the kernels run on."""
+    import torch
+    wl = workloads.workload_n2_fixed(n_traj)
+    probs = [workloads.with_changes(p, ionization="saddle") for p in wl["problems"]]
+    n, seeds = wl["n_traj"], wl["seeds"]
+    stream = torch.cuda.current_stream()
+    ens = sf.Ensemble(sum(n), len(probs))
+    ens, ws = sf.sample_initial(probs, n, seeds, ens=ens)
+    offs, lens = sf.accum_layout(probs)
+    acc = torch.zeros(sum(lens), dtype=torch.float64, device="cuda")
+    v = torch.empty_like(acc)
+    grids = []
+    for p in probs:
+        N, t0, tau = sf.problem_steps(p)
+        grids.append((t0, 0.5 * tau, sf.harmonic_grid(p, 100.0).cuda()))
+    torch.cuda.synchronize()
+    live = live_steps_of(sf, probs, n, ens)
+    samp = []
+
+    def step(timed):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sf.sample_initial(probs, n, seeds, ens=ens, workspace=ws)
+        e1.record(stream)
+        acc.zero_()
+        sf.propagate(probs, ens, accum=acc, workspace=ws)
+        sf.dipole(probs, acc, n, v_out=v)
+        for (t0, tauh, om), o, l in zip(grids, offs, lens):
+            sf.spectrum(v[o:o + l], t0, probs[0]["dt"], tauh, om)
+        if timed:
+            samp.append((e0, e1))
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        step(True)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t) / steps
+    n_live = int((ens.w > 0).sum().item())
+    return {"workload": wl["name"] + "-saddle", "value": live / sec, "unit": "trajectory-steps/s",
+            "ms_per_step": sec * 1e3, "live_trajectory_steps": live, "live_trajectories": n_live,
+            "sample_ms": float(np.mean([a.elapsed_time(b) for a, b in samp])),
+            "precision": "fp64", "ionization": "saddle point of Eq. 2"}
+
+
 def served_variant(sf, n_req, rate_hz, window=1024, h_max=100.0, h_step=0.1, n_groups=2):
     """p50/p99 latency and spectra/s of a seeded Poisson request stream under
     continuous batching (processor sharing and shortest-remaining-work) and
@@ -357,6 +408,9 @@ def main():
                                "tuning": list(tun), "launch": "one HIP graph per step"}
         plan.close()
         del plan
+        torch.cuda.empty_cache()
+        variants["saddle"] = saddle_variant(sf, args.n_traj, args.steps, args.warmup)
+        print(f"saddle: {variants['saddle']}", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         if args.serve_requests > 0:
             variants["served"] = served_variant(sf, args.serve_requests, args.serve_rate)
