@@ -71,6 +71,8 @@ def lib():
         L.orc_run.restype = C.c_int
         L.orc_spectrum.argtypes = [dp, C.c_int32, C.c_double, C.c_double, C.c_double,
                                    dp, C.c_int32, dp, dp, dp]
+        L.orc_gabor.argtypes = [dp, C.c_int32, C.c_double, C.c_double, C.c_double, dp,
+                                C.c_int32, dp, C.c_int32, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -284,3 +286,14 @@ def spectrum(v, t_first, dt, tau_H, omega):
     lib().orc_spectrum(_dp(v), v.size, float(t_first), float(dt), float(tau_H), _dp(om),
                        om.size, _dp(Vr), _dp(Vi), _dp(Y))
     return Vr + 1j * Vi, Y
+
+
+def gabor(v, t_first, dt, sigma, t_c, omega):
+    """(G [n_c, n_omega] complex, yield) of the Gaussian-window transform."""
+    v, tc, om = _arr(v), _arr(t_c), _arr(omega)
+    Gr = np.zeros((tc.size, om.size))
+    Gi = np.zeros_like(Gr)
+    Y = np.zeros_like(Gr)
+    lib().orc_gabor(_dp(v), v.size, float(t_first), float(dt), float(sigma), _dp(tc), tc.size,
+                    _dp(om), om.size, _dp(Gr), _dp(Gi), _dp(Y))
+    return Gr + 1j * Gi, Y

@@ -108,6 +108,13 @@ void orc_spectrum(const double* v, int32_t n_t, double t_first, double dt, doubl
                   const double* omega, int32_t n_omega, double* V_re, double* V_im,
                   double* yield);
 
+/* Gabor time-frequency transform of v on the grid t_first + k dt (k < n_t):
+ * G(t_c, w) = dt sum_k v_k exp(-(t_k - t_c)^2 / (2 sigma^2)) e^{i w t_k},
+ * yield w^2 |G|^2; outputs [n_c][n_omega] row-major */
+void orc_gabor(const double* v, int32_t n_t, double t_first, double dt, double sigma,
+               const double* t_c, int32_t n_c, const double* omega, int32_t n_omega,
+               double* G_re, double* G_im, double* yield);
+
 #ifdef __cplusplus
 }
 #endif
