@@ -9,6 +9,7 @@
  *      summing Re a_jk over trajectories          -> sfhk_propagate
  *   3. normalise the sum into v_z(t_k)             -> sfhk_dipole
  *   4. Hanning-windowed Fourier transform          -> sfhk_spectrum
+ *      (and its time-resolved form                 -> sfhk_gabor)
  *
  * Conventions
  *  - Atomic units, except the laser (nm, W/cm^2, optical cycles, rad).
@@ -215,6 +216,19 @@ sfhk_status sfhk_dipole(const sfhk_problem* probs, int32_t n_prob, const double*
 sfhk_status sfhk_spectrum(const double* v, int32_t n_t, double t_first, double dt, double tau_H,
                           const double* omega, int32_t n_omega, double* V_re, double* V_im,
                           double* yield, void* stream);
+
+/* Gabor time-frequency transform of the dipole (Sec. III.C, the analysis of
+ * long and short trajectories):
+ *   G(t_c, w) = dt sum_k v_k exp(-(t_k - t_c)^2 / (2 sigma^2)) e^{i w t_k},
+ * t_k = t_first + k dt, yield w^2 |G|^2.  The paper gives no window width;
+ * sigma is the caller's (1/(3 w_laser) is the Python default).  Terms with
+ * |t_k - t_c| > 8 sigma (weight < 2e-14) are not summed.
+ * v: device [n_t]; t_c: device [n_c]; omega: device [n_omega];
+ * G_re, G_im, yield: device [n_c][n_omega] row-major.  n_c or n_omega = 0 is a
+ * no-op; sigma and dt must be > 0. */
+sfhk_status sfhk_gabor(const double* v, int32_t n_t, double t_first, double dt, double sigma,
+                       const double* t_c, int32_t n_c, const double* omega, int32_t n_omega,
+                       double* G_re, double* G_im, double* yield, void* stream);
 
 /* ------------------------------------------------------------------ plans
  * A plan runs the whole path -- sampling, packing, propagation, dipole and

@@ -14,7 +14,7 @@ from ._abi import FS_COUNT, FS_CIM, FS_CRE, FS_FLIPS, FS_M, FS_P, FS_Q, FS_S, Sf
 
 __all__ = ["problem_steps", "workspace_bytes", "Ensemble", "sample_initial", "propagate",
            "dipole", "spectrum", "run", "SfhkError", "harmonic_grid", "abi_version", "Plan",
-           "accum_layout"]
+           "accum_layout", "gabor", "gabor_width"]
 
 PRECISION = {"fp64": _abi.FP64, "mixed": _abi.MIXED}
 
@@ -157,6 +157,28 @@ def spectrum(v, t_first, dt, tau_H, omega, stream=None):
         C.c_void_p(omega.data_ptr()), n, C.c_void_p(Vr.data_ptr()), C.c_void_p(Vi.data_ptr()),
         C.c_void_p(Y.data_ptr()), _stream(stream)), "sfhk_spectrum")
     return torch.complex(Vr, Vi), Y
+
+
+def gabor(v, t_first, dt, sigma, t_c, omega, stream=None):
+    """(G complex128 [n_c, n_omega], yield) of the Gaussian-window transform
+    (sfhk_gabor) of v at window centres t_c and frequencies omega."""
+    v = v.contiguous()
+    tc = torch.as_tensor(t_c, dtype=torch.float64).to(v.device).contiguous()
+    om = torch.as_tensor(omega, dtype=torch.float64).to(v.device).contiguous()
+    Gr = torch.empty((tc.numel(), om.numel()), dtype=torch.float64, device=v.device)
+    Gi = torch.empty_like(Gr)
+    Y = torch.empty_like(Gr)
+    _abi.check(_abi.lib().sfhk_gabor(
+        C.c_void_p(v.data_ptr()), v.numel(), float(t_first), float(dt), float(sigma),
+        C.c_void_p(tc.data_ptr()), tc.numel(), C.c_void_p(om.data_ptr()), om.numel(),
+        C.c_void_p(Gr.data_ptr()), C.c_void_p(Gi.data_ptr()), C.c_void_p(Y.data_ptr()),
+        _stream(stream)), "sfhk_gabor")
+    return torch.complex(Gr, Gi), Y
+
+
+def gabor_width(prob):
+    """Default Gabor window width 1/(3 w_laser) of a problem."""
+    return prob["laser"]["lambda_nm"] / (3.0 * 45.56335252912)
 
 
 def harmonic_grid(prob, h_max, h_step=0.05):

@@ -17,7 +17,7 @@ EXPORTS = ["sfhk_abi_version", "sfhk_last_error", "sfhk_problem_steps", "sfhk_wo
            "sfhk_plan_workspace_bytes", "sfhk_plan_create", "sfhk_plan_run", "sfhk_plan_capture",
            "sfhk_plan_replay", "sfhk_plan_destroy", "sfhk_request_bytes", "sfhk_request_layout",
            "sfhk_request_table_bytes", "sfhk_request_init", "sfhk_serve_window",
-           "sfhk_request_finalize"]
+           "sfhk_request_finalize", "sfhk_gabor"]
 
 
 class Center(C.Structure):
@@ -130,6 +130,10 @@ def lib():
         L.sfhk_request_finalize.argtypes = [P, C.c_int32, C.c_void_p, C.c_int32, C.c_int32,
                                             C.c_void_p]
         L.sfhk_request_finalize.restype = C.c_int
+        L.sfhk_gabor.argtypes = [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double,
+                                 C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_void_p]
+        L.sfhk_gabor.restype = C.c_int
         _lib = L
     return _lib
 

@@ -485,6 +485,24 @@ sfhk_status sfhk_spectrum(const double* v, int32_t n_t, double t_first, double d
   return ok();
 }
 
+sfhk_status sfhk_gabor(const double* v, int32_t n_t, double t_first, double dt, double sigma,
+                       const double* t_c, int32_t n_c, const double* omega, int32_t n_omega,
+                       double* G_re, double* G_im, double* yield, void* stream) {
+  if (n_t < 1) return fail(SFHK_E_INVALID, "n_t must be >= 1");
+  if (n_c < 0 || n_omega < 0) return fail(SFHK_E_INVALID, "n_c and n_omega must be >= 0");
+  if (n_c > 0 && (size_t)n_c * (size_t)n_omega > (size_t(1) << 31))
+    return fail(SFHK_E_INVALID, "n_c * n_omega must be <= 2^31");
+  if (!(is_finite(t_first) && is_finite(dt) && dt > 0 && is_finite(sigma) && sigma > 0))
+    return fail(SFHK_E_INVALID, "t_first, dt > 0 and sigma > 0 must be finite");
+  if (n_c == 0 || n_omega == 0) return ok();
+  if (!v || !t_c || !omega || !G_re || !G_im || !yield)
+    return fail(SFHK_E_INVALID, "gabor pointers must be non-null");
+  hipError_t e = launch_gabor(v, n_t, t_first, dt, sigma, t_c, n_c, omega, n_omega, G_re, G_im,
+                              yield, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "gabor");
+  return ok();
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------------ plans

@@ -371,6 +371,83 @@ __global__ void __launch_bounds__(kBlock) spectrum_batched_kernel(const Desc* __
 
 inline unsigned blocks_for(uint64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// --------------------------------------------------------------- Gabor
+// One workgroup per window centre t_c.  The window-weighted signal
+// u_k = v_k exp(-(t_k - t_c)^2 / (2 sigma^2)) over |t_k - t_c| <= 8 sigma
+// (the rest is below 2e-14 of the peak weight) is staged through LDS in
+// chunks; each thread sums u_k e^{i w t_k} for its frequencies, advancing
+// e^{i w t_k} by the rotation e^{i w dt} and re-taking it exactly every 64
+// steps (rounding growth below 64 ulp).
+constexpr int kGaborChunk = 4096;
+
+__global__ void __launch_bounds__(kBlock) gabor_kernel(const double* __restrict__ v, int n_t,
+                                                       double t_first, double dt, double sigma,
+                                                       const double* __restrict__ t_c,
+                                                       const double* __restrict__ omega,
+                                                       int n_omega, double* __restrict__ G_re,
+                                                       double* __restrict__ G_im,
+                                                       double* __restrict__ yield) {
+  __shared__ double u[kGaborChunk];
+  const int a = blockIdx.x;
+  const double tc = t_c[a];
+  const double half = 8.0 * sigma;
+  // clamp in floating point first: a far-away centre must not overflow the cast
+  const double flo = fmax(ceil((tc - half - t_first) / dt), 0.0);
+  const double fhi = fmin(floor((tc + half - t_first) / dt), (double)(n_t - 1));
+  const long long klo = (long long)fmin(flo, (double)n_t);
+  const long long khi = (long long)fmax(fhi, -1.0);
+  const double inv_s = 1.0 / sigma;
+  // each thread keeps the partial sums of up to 8 frequencies
+  constexpr int kPer = 8;
+  for (int b0 = 0; b0 < n_omega; b0 += kBlock * kPer) {
+    double sr[kPer], si[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) sr[j] = si[j] = 0.0;
+    for (long long c0 = klo; c0 <= khi; c0 += kGaborChunk) {
+      const int len = (int)((khi - c0 + 1) < kGaborChunk ? (khi - c0 + 1) : kGaborChunk);
+      __syncthreads();
+      for (int i = threadIdx.x; i < len; i += kBlock) {
+        const double t = t_first + (double)(c0 + i) * dt;
+        const double x = (t - tc) * inv_s;
+        u[i] = v[c0 + i] * exp(-0.5 * x * x);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        const int b = b0 + j * kBlock + threadIdx.x;
+        if (b >= n_omega || len <= 0) continue;
+        const double w = omega[b];
+        double rs, rc;
+        sincos(w * dt, &rs, &rc);
+        double zr = 0.0, zi = 0.0, ar = 0.0, ai = 0.0;
+        for (int i = 0; i < len; ++i) {
+          if ((i & 63) == 0) {
+            sincos(w * (t_first + (double)(c0 + i) * dt), &zi, &zr);
+          } else {
+            const double nr = zr * rc - zi * rs;
+            zi = zr * rs + zi * rc;
+            zr = nr;
+          }
+          ar += u[i] * zr;
+          ai += u[i] * zi;
+        }
+        sr[j] += ar;
+        si[j] += ai;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int b = b0 + j * kBlock + threadIdx.x;
+      if (b >= n_omega) continue;
+      const double gr = dt * sr[j], gi = dt * si[j], w = omega[b];
+      const size_t o = (size_t)a * n_omega + b;
+      G_re[o] = gr;
+      G_im[o] = gi;
+      yield[o] = w * w * (gr * gr + gi * gi);
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
@@ -480,4 +557,15 @@ hipError_t launch_spectrum(const double* v, int n_t, double t_first, double dt, 
   return hipGetLastError();
 }
 
+}  // namespace sfhk
+
+namespace sfhk {
+hipError_t launch_gabor(const double* v, int n_t, double t_first, double dt, double sigma,
+                        const double* t_c, int n_c, const double* omega, int n_omega,
+                        double* G_re, double* G_im, double* yield, hipStream_t s) {
+  if (n_c == 0 || n_omega == 0) return hipSuccess;
+  hipLaunchKernelGGL(gabor_kernel, dim3(n_c), dim3(kBlock), 0, s, v, n_t, t_first, dt, sigma, t_c,
+                     omega, n_omega, G_re, G_im, yield);
+  return hipGetLastError();
+}
 }  // namespace sfhk

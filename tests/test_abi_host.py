@@ -152,3 +152,17 @@ def test_capacity_and_workspace_size_errors(L):
     n = _abi.u64_array([8])
     assert lib.sfhk_sample_initial(p, 1, n, n, n, C.byref(ens), C.c_void_p(64), 16, None) == 2
     assert b"workspace" in lib.sfhk_last_error()
+
+
+def test_gabor_arguments_validated(L):
+    lib = L.lib()
+    fake = C.c_void_p(64)  # never dereferenced: every call below fails or is a no-op
+    args = lambda n_t=10, dt=0.1, sig=1.0, n_c=3, n_w=4, ptr=fake: (
+        ptr, n_t, -5.0, dt, sig, ptr, n_c, ptr, n_w, ptr, ptr, ptr, None)
+    assert lib.sfhk_gabor(*args(n_t=0)) == 1
+    assert lib.sfhk_gabor(*args(dt=0.0)) == 1
+    assert lib.sfhk_gabor(*args(sig=-1.0)) == 1
+    assert lib.sfhk_gabor(*args(n_c=-1)) == 1
+    assert lib.sfhk_gabor(*args(ptr=None)) == 1
+    assert lib.sfhk_gabor(*args(n_c=0)) == 0
+    assert lib.sfhk_gabor(*args(n_w=0)) == 0
