@@ -71,6 +71,8 @@ def lib():
         L.orc_run.restype = C.c_int
         L.orc_spectrum.argtypes = [dp, C.c_int32, C.c_double, C.c_double, C.c_double,
                                    dp, C.c_int32, dp, dp, dp]
+        L.orc_return_step.argtypes = [P, C.c_int32, dp, dp, dp, C.c_double,
+                                      C.POINTER(C.c_int32), dp]
         L.orc_gabor.argtypes = [dp, C.c_int32, C.c_double, C.c_double, C.c_double, dp,
                                 C.c_int32, dp, C.c_int32, dp, dp, dp]
         _lib = L
@@ -297,3 +299,12 @@ def gabor(v, t_first, dt, sigma, t_c, omega):
     lib().orc_gabor(_dp(v), v.size, float(t_first), float(dt), float(sigma), _dp(tc), tc.size,
                     _dp(om), om.size, _dp(Gr), _dp(Gi), _dp(Y))
     return Gr + 1j * Gi, Y
+
+
+def return_step(d, k0, q0, p0, nax, r_ret):
+    """(k_ret or -1, return kinetic energy) of one trajectory."""
+    P = make_problem(d)
+    k, e = C.c_int32(), C.c_double()
+    lib().orc_return_step(C.byref(P), int(k0), _dp(_arr(q0, 3)), _dp(_arr(p0, 3)),
+                          _dp(_arr(nax, 3)), float(r_ret), C.byref(k), C.byref(e))
+    return k.value, e.value

@@ -592,6 +592,40 @@ int orc_trajectory(const orc_problem* P, int32_t k0, int32_t k_end, const double
                    final_state);
 }
 
+/* ------------------------------------------------------------ returns */
+/* Classical return of the trajectory to the molecule (Sec. III.C: long and
+ * short trajectories born in successive half-cycles return in the same time
+ * window).  Reading: a return is the first entry into the sphere of radius
+ * r_ret around the molecular centre after the trajectory has been outside
+ * it; the return energy is the kinetic energy there (the photon energy is
+ * that plus I_p).  The full state is stepped by the same RK4 as above. */
+void orc_return_step(const orc_problem* P, int32_t k0, const double q0[3], const double p0[3],
+                     const double nax[3], double r_ret, int32_t* k_ret, double* e_ret) {
+  int32_t N;
+  orc_laser(P, NULL, NULL, NULL, &N);
+  double y[NY] = {0.0};
+  for (int a = 0; a < 3; ++a) {
+    y[a] = q0[a];
+    y[3 + a] = p0[a];
+  }
+  for (int a = 0; a < 6; ++a) y[6 + 6 * a + a] = 1.0;
+  *k_ret = -1;
+  *e_ret = 0.0;
+  int outside = 0;
+  for (int32_t k = k0;; ++k) {
+    double r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+    if (r >= r_ret) {
+      outside = 1;
+    } else if (outside) {
+      *k_ret = k;
+      *e_ret = 0.5 * (y[3] * y[3] + y[4] * y[4] + y[5] * y[5]);
+      return;
+    }
+    if (k >= N) return;
+    rk4_step(P, nax, k, y);
+  }
+}
+
 /* ------------------------------------------------------------ the ensemble */
 /* Monte Carlo sum over independent trajectories (Sec. II.A-B, Eq. (4)-(6)):
  * accum[k] = sum_j Re a_jk; the dipole velocity is v_k = (2/N_s) accum[k]

@@ -108,6 +108,11 @@ void orc_spectrum(const double* v, int32_t n_t, double t_first, double dt, doubl
                   const double* omega, int32_t n_omega, double* V_re, double* V_im,
                   double* yield);
 
+/* first return of a trajectory born at step k0: the first step k > k0 with
+ * |q_k| < r_ret after some step j (k0 <= j < k) with |q_j| >= r_ret;
+ * *k_ret = -1 if none up to step N; *e_ret = |p|^2/2 at that step */
+void orc_return_step(const orc_problem* P, int32_t k0, const double q0[3], const double p0[3],
+                     const double nax[3], double r_ret, int32_t* k_ret, double* e_ret);
 /* Gabor time-frequency transform of v on the grid t_first + k dt (k < n_t):
  * G(t_c, w) = dt sum_k v_k exp(-(t_k - t_c)^2 / (2 sigma^2)) e^{i w t_k},
  * yield w^2 |G|^2; outputs [n_c][n_omega] row-major */
