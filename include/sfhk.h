@@ -217,6 +217,19 @@ sfhk_status sfhk_spectrum(const double* v, int32_t n_t, double t_first, double d
                           const double* omega, int32_t n_omega, double* V_re, double* V_im,
                           double* yield, void* stream);
 
+/* Classical returns of a sampled ensemble (Sec. III.C: long and short
+ * trajectories born in successive half-cycles return in the same window):
+ * for every live slot the first step k > k0 at which |q_k| < r_return after
+ * some earlier step with |q| >= r_return, and |p_k|^2/2 there (the photon
+ * energy is that plus I_p); -1 and 0 for slots that never return or are not
+ * live.  Only the classical orbit (q, p) is stepped, by the same RK4 as
+ * sfhk_propagate.  k_ret, e_ret: device [capacity], indexed by slot;
+ * workspace as for sfhk_propagate. */
+sfhk_status sfhk_return_steps(const sfhk_problem* probs, int32_t n_prob,
+                              const sfhk_ensemble* ens, double r_return, int32_t* k_ret,
+                              double* e_ret, void* workspace, size_t workspace_bytes,
+                              void* stream);
+
 /* Gabor time-frequency transform of the dipole (Sec. III.C, the analysis of
  * long and short trajectories):
  *   G(t_c, w) = dt sum_k v_k exp(-(t_k - t_c)^2 / (2 sigma^2)) e^{i w t_k},

@@ -14,7 +14,7 @@ from ._abi import FS_COUNT, FS_CIM, FS_CRE, FS_FLIPS, FS_M, FS_P, FS_Q, FS_S, Sf
 
 __all__ = ["problem_steps", "workspace_bytes", "Ensemble", "sample_initial", "propagate",
            "dipole", "spectrum", "run", "SfhkError", "harmonic_grid", "abi_version", "Plan",
-           "accum_layout", "gabor", "gabor_width"]
+           "accum_layout", "gabor", "gabor_width", "return_steps"]
 
 PRECISION = {"fp64": _abi.FP64, "mixed": _abi.MIXED}
 
@@ -157,6 +157,27 @@ def spectrum(v, t_first, dt, tau_H, omega, stream=None):
         C.c_void_p(omega.data_ptr()), n, C.c_void_p(Vr.data_ptr()), C.c_void_p(Vi.data_ptr()),
         C.c_void_p(Y.data_ptr()), _stream(stream)), "sfhk_spectrum")
     return torch.complex(Vr, Vi), Y
+
+
+def return_steps(probs, ens, r_return=4.0, workspace=None, stream=None):
+    """(k_ret int32, e_ret) per slot: first return step into |q| < r_return
+    (-1 if none) and the kinetic energy there (sfhk_return_steps)."""
+    arr = _abi.make_problems(probs)
+    dev = ens.k0.device
+    nb = _abi.lib().sfhk_workspace_bytes(arr, len(probs), ens.capacity)
+    if nb == 0:
+        raise SfhkError(1, "sfhk_workspace_bytes")
+    if workspace is None or workspace.numel() < nb:
+        workspace = torch.empty(nb, dtype=torch.uint8, device=dev)
+    cap = max(ens.capacity, 1)
+    k_ret = torch.empty(cap, dtype=torch.int32, device=dev)
+    e_ret = torch.empty(cap, dtype=torch.float64, device=dev)
+    es = ens.struct()
+    _abi.check(_abi.lib().sfhk_return_steps(
+        arr, len(probs), C.byref(es), float(r_return), C.c_void_p(k_ret.data_ptr()),
+        C.c_void_p(e_ret.data_ptr()), C.c_void_p(workspace.data_ptr()), workspace.numel(),
+        _stream(stream)), "sfhk_return_steps")
+    return k_ret, e_ret
 
 
 def gabor(v, t_first, dt, sigma, t_c, omega, stream=None):

@@ -17,7 +17,7 @@ EXPORTS = ["sfhk_abi_version", "sfhk_last_error", "sfhk_problem_steps", "sfhk_wo
            "sfhk_plan_workspace_bytes", "sfhk_plan_create", "sfhk_plan_run", "sfhk_plan_capture",
            "sfhk_plan_replay", "sfhk_plan_destroy", "sfhk_request_bytes", "sfhk_request_layout",
            "sfhk_request_table_bytes", "sfhk_request_init", "sfhk_serve_window",
-           "sfhk_request_finalize", "sfhk_gabor"]
+           "sfhk_request_finalize", "sfhk_gabor", "sfhk_return_steps"]
 
 
 class Center(C.Structure):
@@ -134,6 +134,10 @@ def lib():
                                  C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_void_p]
         L.sfhk_gabor.restype = C.c_int
+        L.sfhk_return_steps.argtypes = [P, C.c_int32, C.POINTER(Ensemble), C.c_double,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                        C.c_void_p]
+        L.sfhk_return_steps.restype = C.c_int
         _lib = L
     return _lib
 

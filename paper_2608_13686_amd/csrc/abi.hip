@@ -485,6 +485,36 @@ sfhk_status sfhk_spectrum(const double* v, int32_t n_t, double t_first, double d
   return ok();
 }
 
+sfhk_status sfhk_return_steps(const sfhk_problem* probs, int32_t n_prob,
+                              const sfhk_ensemble* ens, double r_return, int32_t* k_ret,
+                              double* e_ret, void* workspace, size_t workspace_bytes,
+                              void* stream) {
+  sfhk_status st = check_problems(probs, n_prob);
+  if (st != SFHK_OK) return st;
+  if ((st = check_ensemble(ens)) != SFHK_OK) return st;
+  if (!(is_finite(r_return) && r_return > 0)) return fail(SFHK_E_INVALID, "r_return must be > 0");
+  if (ens->capacity > 0 && (!k_ret || !e_ret)) return fail(SFHK_E_INVALID, "outputs are null");
+  std::vector<Desc> descs;
+  int64_t max_steps = 0;
+  Layout L = build_layout(probs, n_prob, ens->capacity, &descs, &max_steps);
+  if (!workspace) return fail(SFHK_E_INVALID, "workspace is null");
+  if (workspace_bytes < L.bytes)
+    return fail(SFHK_E_NOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, L.bytes);
+  if (ens->capacity == 0) return ok();
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace ws = carve(workspace, L);
+  if ((st = stage_problems(descs, ws, nullptr, max_steps, s)) != SFHK_OK) return st;
+  const uint64_t max_packs = (ens->capacity + kWave - 1) / kWave + (uint64_t)n_prob;
+  if (max_packs > 0x7fffffffull) return fail(SFHK_E_UNSUPPORTED, "ensemble too large");
+  hipError_t e = launch_fill_i32(k_ret, -1, ens->capacity, s);
+  if (e == hipSuccess) e = launch_fill_f64(e_ret, 0.0, ens->capacity, s);
+  if (e == hipSuccess)
+    e = launch_returns(ws.descs, n_prob, ws.field, ens_ptrs(ens), (uint32_t)max_packs, r_return,
+                       k_ret, e_ret, s);
+  if (e != hipSuccess) return hip_fail(e, "return steps");
+  return ok();
+}
+
 sfhk_status sfhk_gabor(const double* v, int32_t n_t, double t_first, double dt, double sigma,
                        const double* t_c, int32_t n_c, const double* omega, int32_t n_omega,
                        double* G_re, double* G_im, double* yield, void* stream) {

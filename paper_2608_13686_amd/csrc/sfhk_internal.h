@@ -102,6 +102,9 @@ hipError_t launch_sort(const Desc* descs, int n_prob, uint64_t n_slots, uint64_t
 hipError_t launch_fill_i32(int32_t* p, int32_t v, uint64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, uint64_t n, hipStream_t s);
 hipError_t launch_scale(const double* in, double* out, double scale, uint64_t n, hipStream_t s);
+hipError_t launch_returns(const Desc* descs, int n_prob, const double* field, EnsPtrs e,
+                          uint32_t max_packs, double r_ret, int32_t* k_ret, double* e_ret,
+                          hipStream_t s);
 hipError_t launch_gabor(const double* v, int n_t, double t_first, double dt, double sigma,
                         const double* t_c, int n_c, const double* omega, int n_omega,
                         double* G_re, double* G_im, double* yield, hipStream_t s);

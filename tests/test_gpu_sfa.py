@@ -141,3 +141,33 @@ def test_saddle_mixed_precision_error(sf):
         torch.cuda.synchronize()
         out[prec] = acc.cpu().numpy()
     assert rel(out["mixed"], out["fp64"]) < 2e-3
+
+
+@pytest.mark.parametrize("ionization", ["first_order", "saddle"])
+def test_return_steps_match_oracle(sf, orc, ionization):
+    """First classical return (long/short trajectory maps) per trajectory."""
+    import torch
+    probs = [W.with_changes(W.n2(0.0), ionization=ionization),
+             W.with_changes(W.h2_softcore(40.0), ionization=ionization)]
+    n, seeds = [1200, 1200], [21, 22]
+    ens, ws = sf.sample_initial(probs, n, seeds)
+    r_ret = 8.0  # transverse drift makes most orbits miss a smaller sphere
+    k_ret, e_ret = sf.return_steps(probs, ens, r_ret, workspace=ws)
+    torch.cuda.synchronize()
+    k_ret, e_ret = k_ret.cpu().numpy(), e_ret.cpu().numpy()
+    off, checked, returned = 0, 0, 0
+    for p, nn, sd in zip(probs, n, seeds):
+        o = orc.sample(p, sd, 0, nn)
+        for i in range(nn):
+            if o["w"][i] == 0:
+                assert k_ret[off + i] == -1 and e_ret[off + i] == 0.0
+                continue
+            k, e = orc.return_step(p, int(o["k0"][i]), o["q0"][i], o["p0"][i], o["nax"][i], r_ret)
+            assert k_ret[off + i] == k, (p["name"], i)
+            if k >= 0:
+                returned += 1
+                assert abs(e_ret[off + i] - e) <= 1e-9 * max(e, 1e-3)
+            checked += 1
+        off += nn
+    print(f"{checked} live trajectories, {returned} returned", flush=True)
+    assert returned > 40
