@@ -190,6 +190,36 @@ def saddle_variant(sf, n_traj, steps, warmup):
             "precision": "fp64", "ionization": "saddle point of Eq. 2"}
 
 
+def analysis_variant(sf, probs, ens, ws, v, offs, lens):
+    """Time-frequency and return analysis of the headline ensemble: the
+    Gabor map of each dipole (centres every 0.5 a.u. over the pulse,
+    harmonics 0..100 in steps of 0.1, window 1/(3 w)) and the first classical
+    return of every live trajectory (sphere of 8 a.u.), timed with HIP events."""
+    import torch
+    stream = torch.cuda.current_stream()
+    res = {}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(stream)
+    n_pts = 0
+    for p, o, l in zip(probs, offs, lens):
+        N, t0, tau = sf.problem_steps(p)
+        tc = torch.arange(-0.5 * tau, 0.5 * tau, 0.5, dtype=torch.float64)
+        om = sf.harmonic_grid(p, 100.0, 0.1)
+        sf.gabor(v[o:o + l], t0, p["dt"], sf.gabor_width(p), tc, om)
+        n_pts += tc.numel() * om.numel()
+    ev[1].record(stream)
+    ev[2].record(stream)
+    k_ret, e_ret = sf.return_steps(probs, ens, 8.0, workspace=ws)
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    res["gabor_ms"] = ev[0].elapsed_time(ev[1])
+    res["gabor_points"] = n_pts
+    res["returns_ms"] = ev[2].elapsed_time(ev[3])
+    res["returned_trajectories"] = int((k_ret >= 0).sum().item())
+    res["live_trajectories"] = int((ens.w > 0).sum().item())
+    return res
+
+
 def served_variant(sf, n_req, rate_hz, window=1024, h_max=100.0, h_step=0.1, n_groups=2):
     """p50/p99 latency and spectra/s of a seeded Poisson request stream under
     continuous batching (processor sharing and shortest-remaining-work) and
@@ -409,6 +439,8 @@ def main():
         plan.close()
         del plan
         torch.cuda.empty_cache()
+        variants["analysis"] = analysis_variant(sf, probs, ens, ws, v, offs, lens)
+        print(f"analysis: {variants['analysis']}", file=sys.stderr, flush=True)
         variants["saddle"] = saddle_variant(sf, args.n_traj, args.steps, args.warmup)
         print(f"saddle: {variants['saddle']}", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
