@@ -220,6 +220,69 @@ def analysis_variant(sf, probs, ens, ws, v, offs, lens):
     return res
 
 
+def averaging_variant(sf, sizes=(1 << 14, 1 << 16, 1 << 18, 1 << 20), reps=3,
+                      n_ref=1 << 26):
+    """Isotropic H2 two ways at equal trajectory counts (Eq. 5 with ten fixed
+    alignments at Gauss-Legendre nodes in cos(theta), each with N_s/10
+    trajectories, against the joint Monte Carlo over the axis of Eq. 6 with
+    N_s trajectories), both against a joint run with 2^26 trajectories:
+    relative L2 error of the averaged dipole, median |dB| error of the yield
+    at the odd harmonics 5..33 (the plateau below the cutoff), and the
+    trajectory ratio for equal dipole error, (err_standard / err_joint)^2."""
+    import torch
+    av = workloads.workload_averaging("H2", 10)
+    probs_s, wts = av["standard"]
+    joint = av["joint"]
+    N, t0, tau = sf.problem_steps(joint)
+    w0 = 45.56335252912 / joint["laser"]["lambda_nm"]
+    om = torch.tensor([h * w0 for h in range(5, 35, 2)], dtype=torch.float64, device="cuda")
+
+    def joint_v(n, seed):
+        chunk, acc, done = 1 << 23, None, 0
+        while done < n:
+            m = min(chunk, n - done)
+            out = sf.run([joint], [m], [seed], h_max=1.0)
+            a = out["v"][0] * m
+            acc = a if acc is None else acc + a
+            done += m
+            seed += 7919  # independent chunks
+            del out
+        return acc / n
+
+    def standard_v(n, seed):
+        m = max(n // len(probs_s), 1)
+        out = sf.run(probs_s, [m] * len(probs_s), [seed * 31 + i for i in range(len(probs_s))],
+                     h_max=1.0)
+        return sum(w * v for w, v in zip(wts, out["v"]))
+
+    def yield_of(v):
+        _, Y = sf.spectrum(v, t0, joint["dt"], 0.5 * tau, om)
+        return Y.cpu().numpy()
+
+    t = time.perf_counter()
+    ref = joint_v(n_ref, 999)
+    ref_h, ref_y = ref.cpu().numpy(), yield_of(ref)
+    norm = np.linalg.norm(ref_h)
+
+    def errors(v):
+        y = yield_of(v)
+        return (np.linalg.norm(v.cpu().numpy() - ref_h) / norm,
+                float(np.median(np.abs(10 * np.log10(y / ref_y)))))
+
+    rows = []
+    for n in sizes:
+        ej = [errors(joint_v(n, 100 + r)) for r in range(reps)]
+        es = [errors(standard_v(n, 200 + r)) for r in range(reps)]
+        rms = lambda e, i: float(np.sqrt(np.mean([x[i] ** 2 for x in e])))
+        rows.append({"n_traj": n, "rel_l2_joint": rms(ej, 0), "rel_l2_standard": rms(es, 0),
+                     "odd_harmonic_db_joint": rms(ej, 1), "odd_harmonic_db_standard": rms(es, 1),
+                     "trajectory_ratio": (rms(es, 0) / rms(ej, 0)) ** 2})
+    torch.cuda.synchronize()
+    return {"workload": "isotropic-h2-averaging", "reference_trajectories": n_ref,
+            "repetitions": reps, "angles": [round(a, 3) for a in av["thetas_deg"]],
+            "rows": rows, "seconds": time.perf_counter() - t}
+
+
 def served_variant(sf, n_req, rate_hz, window=1024, h_max=100.0, h_step=0.1, n_groups=2):
     """p50/p99 latency and spectra/s of a seeded Poisson request stream under
     continuous batching (processor sharing and shortest-remaining-work) and
@@ -443,6 +506,9 @@ def main():
         print(f"analysis: {variants['analysis']}", file=sys.stderr, flush=True)
         variants["saddle"] = saddle_variant(sf, args.n_traj, args.steps, args.warmup)
         print(f"saddle: {variants['saddle']}", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        variants["averaging"] = averaging_variant(sf)
+        print(f"averaging: {variants['averaging']}", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         if args.serve_requests > 0:
             variants["served"] = served_variant(sf, args.serve_requests, args.serve_rate)

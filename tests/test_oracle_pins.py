@@ -609,3 +609,19 @@ def test_prefactor_cap_truncates_contributions(orc):
         ab, _ = orc.trajectory(big, k0, q0, p0, n, w)
         assert np.array_equal(ab, a)
     assert hit > 0
+
+
+def test_averaging_quadrature_integrates_the_isotropic_density():
+    """The 10 fixed alignments of the standard average integrate any
+    polynomial of cos(theta) up to degree 19 over the isotropic density
+    (1/2) sin(theta) d(theta) on [0, pi] exactly (even polynomials, by the
+    homonuclear symmetry), and the joint problem samples the sphere uniformly."""
+    import workloads as W
+    av = W.workload_averaging("H2", 10)
+    probs, wts = av["standard"]
+    assert abs(sum(wts) - 1.0) < 1e-15
+    xs = [math.cos(p["align"]["theta"]) for p in probs]
+    for k in range(0, 20, 2):
+        exact = 1.0 / (k + 1)  # (1/2) int_{-1}^{1} x^k dx
+        assert abs(sum(w * x ** k for w, x in zip(wts, xs)) - exact) < 1e-14
+    assert av["joint"]["align"] == {"kind": "cos2m", "theta": 0.0, "phi": 0.0, "m": 0}

@@ -146,6 +146,20 @@ def workload_batched(n_per_problem=32768):
             "n_traj": [n_per_problem] * len(probs), "seeds": seeds, "precision": "mixed"}
 
 
+def workload_averaging(mol="H2", n_angles=10):
+    """Isotropic alignment average two ways (Sec. III.B, Eq. 5 and Eq. 6):
+    'standard': n_angles fixed alignments at the Gauss-Legendre nodes of
+    x = cos(theta) on [0, 1] (the homonuclear symmetry theta -> pi - theta
+    folds [-1, 1] onto [0, 1]) with weights summing to 1, each run on its own;
+    'joint': one problem whose axis is drawn uniformly on the sphere with the
+    trajectory (the cos^0 density)."""
+    x, w = np.polynomial.legendre.leggauss(n_angles)
+    make = h2_softcore if mol == "H2" else n2
+    thetas = [math.degrees(math.acos(0.5 * (xi + 1.0))) for xi in x]
+    return {"standard": ([make(th) for th in thetas], [0.5 * wi for wi in w]),
+            "joint": make(align=cos2m(0)), "thetas_deg": thetas}
+
+
 def request_stream(n_requests, rate_hz, seed=1004, n_min=10_000, n_max=4_000_000):
     """Seeded Poisson stream of spectrum requests.
 
