@@ -35,7 +35,7 @@ class Problem(C.Structure):
         ("ionization", C.c_int32),
     ]
 
-IONIZATION = {"first_order": 0, "saddle": 1}
+IONIZATION = {"first_order": 0, "saddle": 1, "saddle_modified": 2}
 
 
 _lib = None

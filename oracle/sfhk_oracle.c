@@ -291,6 +291,71 @@ int orc_sfa_step(const orc_problem* P, double t0, const double kperp[2], const d
   double complex As = vecpot_c(P, ts);
   double kz = A0r - creal(As);
 
+  /* SFHK2 (Sec. III.C, modified saddle-point equation): an extra term
+   * -eta E(t_s).r0 with r0 = R/2.  Reading: eta is the sign for which the
+   * term raises the effective binding energy, as the paper states it does,
+   * so -eta E(t_s).r0 = sgn E(t0) E(t_s) D with D = (R/2)|n_z| (zero at 90
+   * degrees, largest at 0); the tunnelling action gains eta r0.(A(t_s) -
+   * A(t0)), the term whose stationarity in t_s gives the extra term.  The
+   * saddle point is the root (t_t, k_z) of the complex equation
+   *   (k_z + A(t_s) - A(t0))^2 + k_perp^2 + 2 I_p + 2 sgn E(t0) D E(t_s) = 0
+   * reached by Newton steps on the two real unknowns (finite-difference
+   * Jacobian) from the unmodified root for I_p + |E(t0)| D. */
+  double Dm = 0.0;
+  if (P->ionization == ORC_ION_SADDLE_MODIFIED) {
+    Dm = 0.5 * P->R * fabs(n[2]);
+    double kap1 = sqrt(2.0 * (P->Ip + fabs(E0r) * Dm) + kp2);
+    lo = 0.0;
+    hi = -1.0;
+    for (int i = 1; i <= 150; ++i) {
+      double s = (double)i;
+      double h = -sg * cimag(vecpot_c(P, t0 + I * s)) - kap1;
+      if (h >= 0.0) {
+        hi = s;
+        break;
+      }
+      lo = s;
+    }
+    if (hi < 0.0) return -1;
+    for (int it = 0; it < 200; ++it) {
+      double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      double h = -sg * cimag(vecpot_c(P, t0 + I * mid)) - kap1;
+      if (h >= 0.0) hi = mid;
+      else lo = mid;
+    }
+    tt = 0.5 * (lo + hi);
+    kz = A0r - creal(vecpot_c(P, t0 + I * tt));
+    int converged = 0;
+    for (int it = 0; it < 60 && !converged; ++it) {
+      double x[2] = {tt, kz};
+      double complex f0 = 0.0, fd[2];
+      for (int v = 0; v < 3; ++v) {
+        double xx[2] = {x[0], x[1]};
+        double hstep = 1e-7 * (1.0 + fabs(x[v == 2 ? 1 : 0]));
+        if (v > 0) xx[v - 1] += hstep;
+        double complex t = t0 + I * xx[0];
+        double complex kzt = xx[1] + vecpot_c(P, t) - A0r;
+        double complex f = kzt * kzt + kp2 + 2.0 * P->Ip + 2.0 * sg * Dm * field_c(P, t);
+        if (v == 0) f0 = f;
+        else fd[v - 1] = (f - f0) / hstep;
+      }
+      /* solve [Re fd0 Re fd1; Im fd0 Im fd1] d = -(Re f0, Im f0) */
+      double a11 = creal(fd[0]), a12 = creal(fd[1]), a21 = cimag(fd[0]), a22 = cimag(fd[1]);
+      double det = a11 * a22 - a12 * a21;
+      if (det == 0.0) return -1;
+      double d0 = (-creal(f0) * a22 + cimag(f0) * a12) / det;
+      double d1 = (-cimag(f0) * a11 + creal(f0) * a21) / det;
+      tt += d0;
+      kz += d1;
+      if (fabs(d0) < 1e-13 * (1.0 + fabs(tt)) && fabs(d1) < 1e-13 * (1.0 + fabs(kz)))
+        converged = 1;
+    }
+    if (!converged || !(tt > 0.0)) return -1;
+    ts = t0 + I * tt;
+    As = vecpot_c(P, ts);
+  }
+
   /* integrals from t_s to t0 along t = t0 + i s: int_{t_s}^{t0} f dt =
    * -i int_0^{t_t} f(t0 + i s) ds */
   double gx[16], gw[16];
@@ -313,6 +378,8 @@ int orc_sfa_step(const orc_problem* P, double t0, const double kperp[2], const d
   intK2 *= -I;
   double q0z = creal(intA);
   double complex S = P->Ip * ts - 0.5 * intK2;
+  /* SFHK2: eta r0_z (A(t_s) - A(t0)) with eta r0_z = -sgn E(t0) D */
+  S += -sg * Dm * (As - A0r);
 
   /* matrix element and its denominator */
   double complex Es = field_c(P, ts);
@@ -438,7 +505,7 @@ static void sample_one(const orc_problem* P, uint64_t seed, uint64_t j, int32_t 
   double ww = 0.0;
   q0[0] = q0[1] = q0[2] = 0.0;
   *dph = 0.0;
-  if (P->ionization == ORC_ION_SADDLE) {
+  if (P->ionization == ORC_ION_SADDLE || P->ionization == ORC_ION_SADDLE_MODIFIED) {
     /* Monte Carlo over the ionisation amplitude of Eq. (1): t0 uniform on
      * the grid, k_perp from the Gaussian above, the axis from its density;
      * weight |m e^{i S}| over the k_perp density, in units of the

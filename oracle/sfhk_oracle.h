@@ -35,7 +35,7 @@ enum {
 enum { ORC_ALIGN_FIXED = 0, ORC_ALIGN_COS2M = 1 };
 /* ionisation step: first-order tunnel exit with an ADK-like weight, or the
  * complex saddle point of Eq. (2) with the matrix element of Eq. (1) */
-enum { ORC_ION_FIRST_ORDER = 0, ORC_ION_SADDLE = 1 };
+enum { ORC_ION_FIRST_ORDER = 0, ORC_ION_SADDLE = 1, ORC_ION_SADDLE_MODIFIED = 2 };
 
 typedef struct {
   /* laser: linear polarisation along z, sin^2 envelope */
@@ -77,8 +77,10 @@ void orc_prefactor_det(const double M[36], double gamma, double* re, double* im)
 /* exact SFA ionisation step for birth time t0, transverse momentum kperp and
  * axis n: out = {t_t, k_z, q0_z, Re S, Im S, Re m, Im m} with t_s = t0 + i t_t
  * the saddle point, S the tunnelling action S_down^0, q0_z the tunnel exit
- * and m = <kappa|z E(t_s)|psi_0> / sqrt(E(t_s) kappa_z).  Returns 0, or -1
- * when no saddle point exists (the trajectory is not born). */
+ * and m = <kappa|z E(t_s)|psi_0> / sqrt(E(t_s) kappa_z).  With
+ * ionization = ORC_ION_SADDLE_MODIFIED the saddle point and the action are
+ * those of the modified equation (Sec. III.C, SFHK2).  Returns 0, or -1 when
+ * no saddle point exists (the trajectory is not born). */
 int orc_sfa_step(const orc_problem* P, double t0, const double kperp[2], const double n[3],
                  double out[7]);
 /* the laser continued to complex time t = tr + i ti: A(t) and E(t) */

@@ -237,3 +237,64 @@ def test_birth_phase_of_an_s_orbital_in_the_adiabatic_limit(orc):
     d = np.abs(np.exp(1j * s["dph"][big]) - cmath.exp(-0.75j * math.pi))
     # the O(omega) part of Re S - I_p t0 spreads the phases by up to ~0.2 here
     assert np.all(d < 0.3) and np.median(d) < 0.05
+
+
+# ------------------------------------------------------------------ SFHK2
+def modified(p):
+    return W.with_changes(p, ionization="saddle_modified")
+
+
+def test_modified_saddle_point_solves_its_equation(orc):
+    """(k_z + A(t_s) - A(t0))^2 + k_perp^2 + 2 I_p + 2 sgn E(t0) D E(t_s) = 0,
+    D = (R/2)|n_z| (the term -eta E(t_s).r0 of Sec. III.C)."""
+    rng = np.random.default_rng(8)
+    for theta in (0.0, 35.0, 70.0):
+        p = modified(W.n2(theta))
+        Ip, R = p["target"]["Ip"], p["target"]["R"]
+        th = math.radians(theta)
+        n = np.array([math.sin(th), 0.0, math.cos(th)])
+        for _ in range(8):
+            t0 = rng.uniform(-150, 150)
+            kp = rng.normal(0, 0.3, 2)
+            r = orc.sfa_step(p, t0, kp, n)
+            if r is None:
+                continue
+            E0, A0 = orc.field(p, t0)
+            As, Es = orc.field_complex(p, t0, r["tt"])
+            kz = r["kz"] + As - A0
+            f = kz * kz + kp @ kp + 2 * Ip + 2 * math.copysign(1, E0) * 0.5 * R * abs(n[2]) * Es
+            assert abs(f) < 1e-11 and r["tt"] > 0
+
+
+def test_modified_step_raises_the_effective_ionisation_potential(orc):
+    """Quasi-static limit at the field peak: the modified saddle point is the
+    unmodified one for I_p' = I_p + |E| D: t_t -> kappa'/|E|, Im S ->
+    kappa'^3/(3|E|), kappa'^2 = 2 I_p' + k_perp^2 (corrections O(gamma^2))."""
+    for lam, tol in ((8000.0, 0.02), (16000.0, 0.005)):
+        p = modified(W.n2(0.0, laser=dict(W.N2_LASER, lambda_nm=lam, n_cycles=8.0)))
+        w, E0, tau, N = orc.laser(p)
+        Ip, R = p["target"]["Ip"], p["target"]["R"]
+        r = orc.sfa_step(p, 0.0, (0.1, 0.0), (0, 0, 1))
+        E, _ = orc.field(p, 0.0)
+        kap = math.sqrt(2 * (Ip + E * 0.5 * R) + 0.01)
+        assert abs(r["kz"]) < 1e-10
+        assert r["tt"] == pytest.approx(kap / E, rel=tol)
+        assert r["S"].imag == pytest.approx(kap ** 3 / (3 * E), rel=tol)
+        r1 = orc.sfa_step(saddle(p), 0.0, (0.1, 0.0), (0, 0, 1))
+        assert r["S"].imag > r1["S"].imag  # stronger suppression: a larger effective I_p
+
+
+def test_modified_step_vanishes_at_90_degrees_and_is_inversion_symmetric(orc):
+    p90 = W.n2(90.0)
+    n90 = (1.0, 0.0, math.cos(math.radians(90.0)))
+    for t0 in (4.0, -33.0):
+        a = orc.sfa_step(modified(p90), t0, (0.1, 0.05), n90)
+        b = orc.sfa_step(saddle(p90), t0, (0.1, 0.05), n90)
+        assert abs(a["S"] - b["S"]) < 1e-10 and abs(a["m"] - b["m"]) < 1e-10 * abs(b["m"])
+    p = modified(W.n2(30.0))
+    n = np.array([0.5, 0.0, math.sqrt(0.75)])
+    for t0 in (4.0, -33.0):
+        a = orc.sfa_step(p, t0, (0.1, 0.05), n)
+        b = orc.sfa_step(p, t0, (0.1, 0.05), -n)
+        assert abs(a["S"] - b["S"]) < 1e-12 and abs(a["m"] - b["m"]) < 1e-12 * abs(a["m"])
+        assert a["tt"] == b["tt"] and a["kz"] == b["kz"]
