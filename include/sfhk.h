@@ -58,7 +58,15 @@ typedef enum { SFHK_ALIGN_FIXED = 0, SFHK_ALIGN_COS2M = 1 } sfhk_align_kind;
  * Re int A, and the amplitude of Eq. 1 (matrix element of r.E(t_s) over
  * sqrt(E.kappa), times e^{i(S_down^0 + p0.q0)}) split into the weight w (its
  * modulus over the k_perp proposal density) and the birth phase dph. */
-typedef enum { SFHK_ION_FIRST_ORDER = 0, SFHK_ION_SADDLE = 1 } sfhk_ionization;
+typedef enum {
+  SFHK_ION_FIRST_ORDER = 0,
+  SFHK_ION_SADDLE = 1,
+  /* SADDLE with the modified equation of Sec. III.C (SFHK2): the extra term
+   * -eta E(t_s).r0, r0 = R/2, with eta the sign for which it raises the
+   * binding energy (sgn E(t0) E(t_s) (R/2)|n_z|), and the matching action
+   * term eta r0.(A(t_s) - A(t0)) */
+  SFHK_ION_SADDLE_MODIFIED = 2
+} sfhk_ionization;
 
 /* One centre of the two-centre model potential (Eq. 7, Table I):
  * V_i = -[Zinf + dZ exp(-alpha rho)] / rho, rho = sqrt(|r - R_i|^2 + eps2).

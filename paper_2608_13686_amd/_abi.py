@@ -59,7 +59,7 @@ class Ensemble(C.Structure):
                 ("pack_start", C.c_void_p)]
 
 
-IONIZATION = {"first_order": 0, "saddle": 1}
+IONIZATION = {"first_order": 0, "saddle": 1, "saddle_modified": 2}
 
 
 class Tuning(C.Structure):

@@ -70,11 +70,12 @@ sfhk_status check_problem(const sfhk_problem* p, int idx) {
     return fail(SFHK_E_INVALID, "problem %d: sigma_perp must be >= 0", idx);
   if (!is_finite(p->c_max)) return fail(SFHK_E_INVALID, "problem %d: c_max not finite", idx);
   if (p->n_steps < 0) return fail(SFHK_E_INVALID, "problem %d: n_steps must be >= 0", idx);
-  if (p->ionization != SFHK_ION_FIRST_ORDER && p->ionization != SFHK_ION_SADDLE)
+  if (p->ionization != SFHK_ION_FIRST_ORDER && p->ionization != SFHK_ION_SADDLE &&
+      p->ionization != SFHK_ION_SADDLE_MODIFIED)
     return fail(SFHK_E_INVALID, "problem %d: unknown ionisation step %d", idx, p->ionization);
   // the saddle-point step writes the pulse as carriers w and w +- 2 pi/tau;
   // one cycle makes w - 2 pi/tau vanish
-  if (p->ionization == SFHK_ION_SADDLE && !(p->las.n_cycles > 1.0))
+  if (p->ionization != SFHK_ION_FIRST_ORDER && !(p->las.n_cycles > 1.0))
     return fail(SFHK_E_INVALID, "problem %d: the saddle-point step needs n_cycles > 1", idx);
   const sfhk_target& T = p->tgt;
   if (!(is_finite(T.R) && T.R >= 0)) return fail(SFHK_E_INVALID, "problem %d: R must be >= 0", idx);

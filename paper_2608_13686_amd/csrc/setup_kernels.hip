@@ -112,7 +112,7 @@ __global__ void sample_kernel(const Desc* __restrict__ descs, int n_prob,
   double E = field[d.field_off + 2 * (uint64_t)k0];
   double F = fabs(E);
   double w = 0.0, qz = 0.0, pz = 0.0, dph = 0.0;
-  if (d.ionization == SFHK_ION_SADDLE) {
+  if (d.ionization != SFHK_ION_FIRST_ORDER) {
     const double nn[3] = {nx, ny, nz};
     SfaBirth b;
     if (sfa_birth(d, d.t_first + (double)k0 * d.dt, px, py, nn, b)) {
