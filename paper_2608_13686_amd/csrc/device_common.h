@@ -122,7 +122,10 @@ struct StepMatrix {
   T d[3][3];  // P22
 };
 
-template <typename T>
+// With Inc = true the identity is left out of P11 and P22 (the step is then
+// applied as an increment, apply_step_increment), so that their small
+// O(h^2 K) parts keep full relative precision in FP32.
+template <typename T, bool Inc = false>
 __device__ __forceinline__ void rk4_step_matrix(const T K1[6], const T K2[6], const T K3[6],
                                                 const T K4[6], T h, StepMatrix<T>& P) {
   const T c2 = h * h / T(6), c3 = h * h * h / T(12), c4 = h * h * h * h / T(24), c1 = h / T(6);
@@ -138,13 +141,29 @@ __device__ __forceinline__ void rk4_step_matrix(const T K1[6], const T K2[6], co
       const T q42 = K4[sym_idx(r, 0)] * K2[sym_idx(0, c)] + K4[sym_idx(r, 1)] * K2[sym_idx(1, c)] +
                     K4[sym_idx(r, 2)] * K2[sym_idx(2, c)];
       const int i = sym_idx(r, c);
-      const T dl = r == c ? T(1) : T(0);
+      const T dl = (r == c && !Inc) ? T(1) : T(0);
       P.a[r][c] = dl - c2 * (K1[i] + s23[i]) + c4 * q31;
       P.d[r][c] = dl - c2 * (s23[i] + K4[i]) + c4 * q42;
       P.c[r][c] = c3 * (q31 + q42) - c1 * (K1[i] + K4[i] + T(2) * s23[i]);
     }
 #pragma unroll
   for (int i = 0; i < 6; ++i) P.b[i] = (i < 3 ? h : T(0)) - c3 * s23[i];
+}
+
+// One monodromy column through a step matrix built with Inc = true:
+// (x, v) + (P11 - I, P12; P21, P22 - I)(x, v).
+template <typename T>
+__device__ __forceinline__ void apply_step_increment(const StepMatrix<T>& P, const T x[3],
+                                                     const T v[3], T xn[3], T vn[3]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const T dx = P.a[r][0] * x[0] + P.a[r][1] * x[1] + P.a[r][2] * x[2] +
+                 P.b[sym_idx(r, 0)] * v[0] + P.b[sym_idx(r, 1)] * v[1] + P.b[sym_idx(r, 2)] * v[2];
+    const T dv = P.c[r][0] * x[0] + P.c[r][1] * x[1] + P.c[r][2] * x[2] + P.d[r][0] * v[0] +
+                 P.d[r][1] * v[1] + P.d[r][2] * v[2];
+    xn[r] = x[r] + dx;
+    vn[r] = v[r] + dv;
+  }
 }
 
 // One monodromy column (x, v) = (dq/dz_c, dp/dz_c) through the step matrix.

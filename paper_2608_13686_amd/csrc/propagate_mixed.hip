@@ -149,44 +149,22 @@ __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
       }
       S = S + (hd / 6.0) * (double)sS;
     }
+    // monodromy: M <- M + (P - I) M with the RK4 step matrix of K1..K4,
+    // its identity part left out so that FP32 keeps the O(h^2 K) terms
+    {
+      StepMatrix<float> P;
+      rk4_step_matrix<float, true>(K1, K2, K3, K4, h, P);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      const float x0[3] = {mq[0][c], mq[1][c], mq[2][c]};
-      const float v0[3] = {mp[0][c], mp[1][c], mp[2][c]};
-      float a[3], xs[3], vs[3], sx[3], sv[3];
-      symmul(K1, x0, a);
+      for (int c = 0; c < 6; ++c) {
+        const float x0[3] = {mq[0][c], mq[1][c], mq[2][c]};
+        const float v0[3] = {mp[0][c], mp[1][c], mp[2][c]};
+        float xn[3], vn[3];
+        apply_step_increment(P, x0, v0, xn, vn);
 #pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        sx[r] = v0[r];
-        sv[r] = -a[r];
-        xs[r] = x0[r] + hh * v0[r];
-        vs[r] = v0[r] - hh * a[r];
-      }
-      symmul(K2, xs, a);
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const float kx = vs[r];
-        sx[r] += 2.0f * kx;
-        sv[r] -= 2.0f * a[r];
-        xs[r] = x0[r] + hh * kx;
-        vs[r] = v0[r] - hh * a[r];
-      }
-      symmul(K3, xs, a);
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const float kx = vs[r];
-        sx[r] += 2.0f * kx;
-        sv[r] -= 2.0f * a[r];
-        xs[r] = x0[r] + h * kx;
-        vs[r] = v0[r] - h * a[r];
-      }
-      symmul(K4, xs, a);
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        sx[r] += vs[r];
-        sv[r] -= a[r];
-        mq[r][c] = x0[r] + h6 * sx[r];
-        mp[r][c] = v0[r] + h6 * sv[r];
+        for (int r = 0; r < 3; ++r) {
+          mq[r][c] = xn[r];
+          mp[r][c] = vn[r];
+        }
       }
     }
     // FP32 rounding is amplified by the monodromy matrix: past the bound the
