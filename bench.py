@@ -123,10 +123,23 @@ def spectral_db(sf, prob, v_a, v_b, h_lo, h_hi):
     return float(np.median(db)), float(np.percentile(db, 90))
 
 
+_SIDE = None
+
+
+def side_stream():
+    """One side stream for every recorded graph: each extra stream takes a
+    hardware queue of the process's few."""
+    global _SIDE
+    import torch
+    if _SIDE is None:
+        _SIDE = torch.cuda.Stream()
+    return _SIDE
+
+
 def timed_plan(sf, probs, n_traj, seeds, precision, tuning, steps, warmup, h_max):
     import torch
     plan = sf.Plan(probs, n_traj, seeds, precision=precision, tuning=tuning, h_max=h_max)
-    side = torch.cuda.Stream()
+    side = side_stream()
     plan.capture(side)
     for _ in range(max(warmup, 1)):
         plan.replay(side)

@@ -32,9 +32,16 @@ def cache_key(probs, precision):
     return f"{arch}_{precision}_{'+'.join(kinds)}_g{'-'.join(map(str, prims))}"
 
 
+_SIDE = {}
+
+
 def time_plan(probs, n_traj, seeds, precision, tuning, reps=2, h_max=40.0):
     plan = Plan(probs, n_traj, seeds, precision=precision, tuning=tuning, h_max=h_max)
-    side = torch.cuda.Stream()
+    # one side stream for all candidates: each stream holds a hardware queue
+    dev = torch.cuda.current_device()
+    if dev not in _SIDE:
+        _SIDE[dev] = torch.cuda.Stream()
+    side = _SIDE[dev]
     plan.capture(side)
     plan.replay(side)  # warm-up
     side.synchronize()

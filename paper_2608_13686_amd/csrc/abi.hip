@@ -387,7 +387,7 @@ sfhk_status sfhk_sample_initial(const sfhk_problem* probs, int32_t n_prob,
   EnsPtrs ep = ens_ptrs(ens);
   hipError_t e = launch_fill_u32(ws.hist, 0u, L.n_bins + 1, s);
   if (e == hipSuccess) e = launch_sample(ws.descs, n_prob, ws.slot_off, n_slots, ws.field, ep,
-                                         ws.hist, s);
+                                         ws.hist, any_saddle(descs.data(), n_prob), s);
   PackOut po{ep.order, ep.live_start, ep.live_count, ep.pack_start};
   if (e == hipSuccess)
     e = launch_sort(ws.descs, n_prob, n_slots, L.n_bins, ws.hist, ws.cursor, ep, nullptr, po, s);
@@ -573,7 +573,8 @@ sfhk_status plan_enqueue(sfhk_plan* P, hipStream_t s) {
   const uint32_t mp = P->L.max_packs;
   hipError_t e = launch_fill_u32(ws.hist, 0u, P->L.n_bins + 1, s);
   if (e == hipSuccess)
-    e = launch_sample(ws.descs, n_prob, ws.slot_off, P->n_slots, ws.field, ep, ws.hist, s);
+    e = launch_sample(ws.descs, n_prob, ws.slot_off, P->n_slots, ws.field, ep, ws.hist,
+                      any_saddle(P->descs.data(), n_prob), s);
   PackOut po{ep.order, ep.live_start, ep.live_count, ep.pack_start};
   if (e == hipSuccess)
     e = launch_sort(ws.descs, n_prob, P->n_slots, P->L.n_bins, ws.hist, ws.cursor, ep, nullptr,

@@ -145,7 +145,8 @@ sfhk_status sfhk_request_init(const sfhk_problem* p, uint64_t n_traj, uint64_t s
   double* field = reinterpret_cast<double*>(b + L.field);
   if (e == hipSuccess) e = launch_field(ddev, 1, field, (uint64_t)N + 1, s);
   if (e == hipSuccess) e = launch_fill_u32(hist, 0u, (uint64_t)N + 2, s);
-  if (e == hipSuccess) e = launch_sample(ddev, 1, slot_off, n_traj, r.field, ep, hist, s);
+  if (e == hipSuccess)
+    e = launch_sample(ddev, 1, slot_off, n_traj, r.field, ep, hist, any_saddle(&r.desc, 1), s);
   PackOut po{r.order, r.live_start, r.live_count, r.pack_start};
   if (e == hipSuccess)
     e = launch_sort(ddev, 1, n_traj, (uint64_t)N + 1, hist, cursor, ep, nullptr, po, s);

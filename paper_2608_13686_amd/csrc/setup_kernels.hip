@@ -75,6 +75,10 @@ __device__ inline int find_problem(const uint64_t* __restrict__ off, int n_prob,
 // the birth time: p0 = (sigma g1, sigma g2, 0), q0 = -(Ip + p0^2/2)/E(t0) z,
 // weight w = (F0/F)^{(2/kappa-1)/2} exp(-(kappa^3/3)(1/F - 1/F0)), F = |E(t0)|,
 // dropped (w = 0) below w_cut; axis fixed or cos^(2m)-distributed (Eq. 6).
+// Saddle = false is the sampler for first-order problems only: it carries no
+// saddle-point code and so no per-lane stack, which every dispatch of a
+// kernel with one would have to be given.
+template <bool Saddle>
 __global__ void sample_kernel(const Desc* __restrict__ descs, int n_prob,
                               const uint64_t* __restrict__ slot_off, uint64_t n_slots,
                               const double* __restrict__ field, EnsPtrs e,
@@ -112,7 +116,7 @@ __global__ void sample_kernel(const Desc* __restrict__ descs, int n_prob,
   double E = field[d.field_off + 2 * (uint64_t)k0];
   double F = fabs(E);
   double w = 0.0, qz = 0.0, pz = 0.0, dph = 0.0;
-  if (d.ionization != SFHK_ION_FIRST_ORDER) {
+  if (Saddle && d.ionization != SFHK_ION_FIRST_ORDER) {
     const double nn[3] = {nx, ny, nz};
     SfaBirth b;
     if (sfa_birth(d, d.t_first + (double)k0 * d.dt, px, py, nn, b)) {
@@ -466,10 +470,14 @@ hipError_t launch_field(const Desc* descs, int n_prob, double* field, uint64_t n
 
 hipError_t launch_sample(const Desc* descs, int n_prob, const uint64_t* slot_off,
                          uint64_t n_slots, const double* field, EnsPtrs e, uint32_t* hist,
-                         hipStream_t s) {
+                         bool saddle, hipStream_t s) {
   if (n_slots == 0) return hipSuccess;
-  hipLaunchKernelGGL(sample_kernel, dim3(blocks_for(n_slots, kBlock)), dim3(kBlock), 0, s, descs,
-                     n_prob, slot_off, n_slots, field, e, hist);
+  if (saddle)
+    hipLaunchKernelGGL(sample_kernel<true>, dim3(blocks_for(n_slots, kBlock)), dim3(kBlock), 0, s,
+                       descs, n_prob, slot_off, n_slots, field, e, hist);
+  else
+    hipLaunchKernelGGL(sample_kernel<false>, dim3(blocks_for(n_slots, kBlock)), dim3(kBlock), 0,
+                       s, descs, n_prob, slot_off, n_slots, field, e, hist);
   return hipGetLastError();
 }
 

@@ -41,6 +41,14 @@ struct Desc {
   double c_max2;       // prefactor cap squared (0: none)
 };
 
+// True if any problem is born by the saddle-point step (it selects the
+// sampler with that code).
+inline bool any_saddle(const Desc* descs, int n) {
+  for (int i = 0; i < n; ++i)
+    if (descs[i].ionization != SFHK_ION_FIRST_ORDER) return true;
+  return false;
+}
+
 // Device pointers of the ensemble, passed by value to kernels.
 struct EnsPtrs {
   int32_t* k0;
@@ -91,7 +99,7 @@ hipError_t launch_field(const Desc* descs, int n_prob, double* field, uint64_t n
                         hipStream_t s);
 hipError_t launch_sample(const Desc* descs, int n_prob, const uint64_t* slot_off,
                          uint64_t n_slots, const double* field, EnsPtrs e, uint32_t* hist,
-                         hipStream_t s);
+                         bool saddle, hipStream_t s);
 // Counts slot i (select ? select[i] >= 0 : w[i] > 0) into bin acc_off[prob] + k0.
 hipError_t launch_count(const Desc* descs, uint64_t n_slots, EnsPtrs e, const int32_t* select,
                         uint32_t* hist, hipStream_t s);

@@ -93,8 +93,10 @@ class HipExecutor:
     """Device side of the server: a torch uint8 pool, the request table and
     the C ABI calls.  Requests are sampled and finalised on the main stream;
     their packs are split into `n_groups` interleaved groups, each advanced by
-    its own stream, so that the tail of one group's window overlaps the
-    others' windows.  All streams have the default priority."""
+    its own stream (group 0 by the main stream itself), so that the tail of
+    one group's window overlaps the others' windows.  All streams have the
+    default priority.  The streams need hardware queues of their own (a
+    process has 4 by default) for the overlap to happen."""
 
     def __init__(self, pool_bytes, max_requests, n_omega, h_step, device="cuda", stream=None,
                  n_groups=2):
@@ -109,7 +111,8 @@ class HipExecutor:
         self.stream = stream or torch.cuda.current_stream()
         self._h = C.c_void_p(self.stream.cuda_stream)
         self.n_groups = int(n_groups)
-        self.group_streams = [torch.cuda.Stream(device=device) for _ in range(self.n_groups)]
+        self.group_streams = [self.stream] + [torch.cuda.Stream(device=device)
+                                              for _ in range(self.n_groups - 1)]
 
     def footprint(self, problem, n_traj):
         arr = _abi.make_problems([problem])
@@ -135,7 +138,7 @@ class HipExecutor:
             C.c_void_p(self.table.data_ptr()), self.max_requests, req.slot, self._h),
             "sfhk_request_init")
         ev = self._event(self.stream)
-        for gs in self.group_streams:
+        for gs in self.group_streams[1:]:
             gs.wait_event(ev)
 
     def window(self, entries, group=0):
@@ -153,7 +156,7 @@ class HipExecutor:
         return self._event(gs)
 
     def finalize(self, req):
-        for gs in self.group_streams:
+        for gs in self.group_streams[1:]:
             self.stream.wait_event(self._event(gs))
         _abi.check(_abi.lib().sfhk_request_finalize(
             req.handle, self.n_omega, C.c_void_p(self.table.data_ptr()),
@@ -162,7 +165,7 @@ class HipExecutor:
 
     def retire(self, req):
         """Event after which no queued work touches the request's memory."""
-        for gs in self.group_streams:
+        for gs in self.group_streams[1:]:
             self.stream.wait_event(self._event(gs))
         return self._event(self.stream)
 
