@@ -70,7 +70,8 @@ typedef enum {
 
 /* One centre of the two-centre model potential (Eq. 7, Table I):
  * V_i = -[Zinf + dZ exp(-alpha rho)] / rho, rho = sqrt(|r - R_i|^2 + eps2).
- * eps2 = 0 is Eq. 7 itself; dZ = 0 is a soft-core Coulomb centre. */
+ * eps2 = 0 is Eq. 7 itself; dZ = 0 is a soft-core Coulomb centre.
+ * Requires eps2 >= 0 and alpha >= 0 (a screening that decays). */
 typedef struct {
   double Zinf, dZ, alpha, eps2;
 } sfhk_center;

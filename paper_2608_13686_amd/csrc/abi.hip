@@ -82,7 +82,8 @@ sfhk_status check_problem(const sfhk_problem* p, int idx) {
   if (!(is_finite(T.Ip) && T.Ip > 0)) return fail(SFHK_E_INVALID, "problem %d: Ip must be > 0", idx);
   for (int c = 0; c < 2; ++c) {
     const sfhk_center& C = T.ctr[c];
-    if (!(is_finite(C.Zinf) && is_finite(C.dZ) && is_finite(C.alpha) && is_finite(C.eps2) && C.eps2 >= 0))
+    if (!(is_finite(C.Zinf) && is_finite(C.dZ) && is_finite(C.alpha) && is_finite(C.eps2) && C.eps2 >= 0 &&
+          C.alpha >= 0))
       return fail(SFHK_E_INVALID, "problem %d: centre %d parameters invalid", idx, c);
   }
   if (T.n_gto < 1 || T.n_gto > SFHK_MAX_GTO)
@@ -152,6 +153,10 @@ Desc make_desc(const sfhk_problem& p) {
     d.dZ[c] = p.tgt.ctr[c].dZ;
     d.alpha[c] = p.tgt.ctr[c].alpha;
     d.eps2[c] = p.tgt.ctr[c].eps2;
+    d.adZ[c] = d.alpha[c] * d.dZ[c];
+    d.a2dZ[c] = d.alpha[c] * d.adZ[c];
+    d.fadZ[c] = (float)d.adZ[c];
+    d.fa2dZ[c] = (float)d.a2dZ[c];
     d.fZinf[c] = (float)d.Zinf[c];
     d.fdZ[c] = (float)d.dZ[c];
     d.falpha[c] = (float)d.alpha[c];
@@ -171,15 +176,35 @@ Desc make_desc(const sfhk_problem& p) {
   d.g_inv4k_min = 1e300;
   for (int j = 0; j < p.tgt.n_gto; ++j) {
     const sfhk_gto& G = p.tgt.gto[j];
-    const double k2 = 1.0 / (4.0 * G.a) + 1.0 / (2.0 * g);
     d.g_l[j] = G.l | (G.center << 1);
     d.g_ion[j] = G.c * std::pow(2.0 * G.a, -1.5);
-    d.g_inv4k[j] = 1.0 / (4.0 * k2);
-    d.g_inv2k[j] = 1.0 / (2.0 * k2);
-    d.g_norm[j] = G.c * std::pow(2.0 * G.a, -1.5) * std::pow(kPi * g, -0.75) *
-                  std::pow(kPi / k2, 1.5);
     d.g_i2a[j] = 1.0 / (2.0 * G.a);
-    d.g_inv4k_min = std::min(d.g_inv4k_min, d.g_inv4k[j]);
+  }
+  // recombination shells, centre 0 first
+  d.n_shell = 0;
+  for (int c = 0; c < 2; ++c) {
+    const int first = d.n_shell;
+    for (int j = 0; j < p.tgt.n_gto; ++j) {
+      const sfhk_gto& G = p.tgt.gto[j];
+      if (G.center != c) continue;
+      const double k2 = 1.0 / (4.0 * G.a) + 1.0 / (2.0 * g);
+      const double inv4k = 1.0 / (4.0 * k2);
+      int s = first;
+      while (s < d.n_shell && d.sh_inv4k[s] != inv4k) ++s;
+      if (s == d.n_shell) {
+        d.sh_inv4k[s] = inv4k;
+        d.sh_ns[s] = d.sh_np[s] = 0.0;
+        ++d.n_shell;
+      }
+      const double norm = G.c * std::pow(2.0 * G.a, -1.5) * std::pow(kPi * g, -0.75) *
+                          std::pow(kPi / k2, 1.5);
+      if (G.l == 0)
+        d.sh_ns[s] += norm;
+      else
+        d.sh_np[s] += norm / (2.0 * G.a);
+      d.g_inv4k_min = std::min(d.g_inv4k_min, inv4k);
+    }
+    if (c == 0) d.n_shell0 = d.n_shell;
   }
   return d;
 }

@@ -18,8 +18,113 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 
 __device__ __forceinline__ double rsqrt_t(double x) { return rsqrt_nr(x); }
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double exp_t(double x) { return exp(x); }
-__device__ __forceinline__ float exp_t(float x) { return __expf(x); }
+
+// Arithmetic with double constants that are built in an SGPR pair where
+// they are used.  The step loops leave no registers for long-lived
+// constants: the compiler hoists plain literals out of the loop and then
+// spills them to scratch or copies them into VGPRs at every use (it prefers
+// the two-address FMAC form, whose addend must be a VGPR).  Here the scalar
+// moves are volatile (never hoisted) and the FMA is the three-address VOP3
+// form, which reads the SGPR pair directly.
+constexpr uint64_t dbits(double x) { return __builtin_bit_cast(uint64_t, x); }
+template <uint64_t B>
+__device__ __forceinline__ double sconst() {
+  uint32_t lo, hi;
+  asm volatile("s_mov_b32 %0, %1" : "=s"(lo) : "i"((uint32_t)(B & 0xffffffffu)));
+  asm volatile("s_mov_b32 %0, %1" : "=s"(hi) : "i"((uint32_t)(B >> 32)));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+// a b + C
+template <uint64_t C>
+__device__ __forceinline__ double fma_k(double a, double b) {
+  double d;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(sconst<C>()));
+  return d;
+}
+// c - a C
+template <uint64_t C>
+__device__ __forceinline__ double fnma_k(double a, double c) {
+  double d;
+  asm("v_fma_f64 %0, -%1, %2, %3" : "=v"(d) : "v"(a), "s"(sconst<C>()), "v"(c));
+  return d;
+}
+// a C
+template <uint64_t C>
+__device__ __forceinline__ double mul_k(double a) {
+  double d;
+  asm("v_mul_f64 %0, %1, %2" : "=v"(d) : "v"(a), "s"(sconst<C>()));
+  return d;
+}
+// a + C
+template <uint64_t C>
+__device__ __forceinline__ double add_k(double a) {
+  double d;
+  asm("v_add_f64 %0, %1, %2" : "=v"(d) : "v"(a), "s"(sconst<C>()));
+  return d;
+}
+// -a C - b
+template <uint64_t C>
+__device__ __forceinline__ double fnms_k(double a, double b) {
+  double d;
+  asm("v_fma_f64 %0, -%1, %2, -%3" : "=v"(d) : "v"(a), "s"(sconst<C>()), "v"(b));
+  return d;
+}
+
+// e^{-y} for 0 <= y <= 708.  -y = n ln2 + r with n = rint(-y / ln2) and
+// |r| <= ln2/2 (the first FMA of the reduction is exact; the low part of
+// ln2 corrects the rest); e^r = 1 + r (1 + r q(r)) with q a degree-9
+// Chebyshev fit of (e^r - 1 - r) / r^2 on |r| <= ln2/2; 2^n by ldexp.
+// Error < 0.7 ulp for results in the normal range; no range checks.
+__device__ __forceinline__ double exp_neg(double y) {
+  const double n = __builtin_rint(mul_k<dbits(-1.4426950408889634)>(y));
+  double r = fnms_k<dbits(0.6931471805599453)>(n, y);
+  r = fnma_k<dbits(2.3190468138462996e-17)>(n, r);
+  double q = add_k<dbits(2.7620075879983367e-07)>(mul_k<dbits(2.5100375832561234e-08)>(r));
+  q = fma_k<dbits(2.7557268480310024e-06)>(q, r);
+  q = fma_k<dbits(2.4801521322368692e-05)>(q, r);
+  q = fma_k<dbits(0.00019841269863040545)>(q, r);
+  q = fma_k<dbits(0.0013888888917196719)>(q, r);
+  q = fma_k<dbits(0.008333333333330065)>(q, r);
+  q = fma_k<dbits(0.041666666666624164)>(q, r);
+  q = fma_k<dbits(0.16666666666666669)>(q, r);
+  q = fma_k<dbits(0.5000000000000001)>(q, r);
+  q = fma(q, r, 1.0);
+  q = fma(q, r, 1.0);
+  return __builtin_amdgcn_ldexp(q, (int)n);
+}
+__device__ __forceinline__ double exp_neg_t(double y) { return exp_neg(y); }
+
+// sin x and cos x for |x| < 2^31.  x = n pi/2 + r with n = rint(2x/pi) and
+// |r| <= pi/4 (pi/2 in two parts; the first FMA is exact); on |r| <= pi/4,
+// sin r = r + r z S(z) and cos r = 1 - z/2 + z^2 C(z), z = r^2, with S and C
+// degree-5 Chebyshev fits of (sin r / r - 1) / z and (cos r - 1 + z/2) / z^2;
+// the quadrant n mod 4 swaps and negates.  Absolute error < 2^-52.
+__device__ __forceinline__ void sincos_k(double x, double& sn, double& cs) {
+  const double n = __builtin_rint(mul_k<dbits(0.6366197723675814)>(x));
+  double r = fnma_k<dbits(1.5707963267948966)>(n, x);
+  r = fnma_k<dbits(6.123233995736766e-17)>(n, r);
+  const double z = r * r;
+  double ps = add_k<dbits(-2.5051131845003624e-08)>(mul_k<dbits(1.5918129294866608e-10)>(z));
+  ps = fma_k<dbits(2.755731610255244e-06)>(ps, z);
+  ps = fma_k<dbits(-0.00019841269836758574)>(ps, z);
+  ps = fma_k<dbits(0.008333333333330948)>(ps, z);
+  ps = fma_k<dbits(-0.16666666666666666)>(ps, z);
+  double pc = add_k<dbits(2.08761462684032e-09)>(mul_k<dbits(-1.1382632425521717e-11)>(z));
+  pc = fma_k<dbits(-2.7557317271729793e-07)>(pc, z);
+  pc = fma_k<dbits(2.480158729876569e-05)>(pc, z);
+  pc = fma_k<dbits(-0.0013888888888887398)>(pc, z);
+  pc = fma_k<dbits(0.041666666666666664)>(pc, z);
+  const double s_r = fma(r * z, ps, r);
+  const double c_r = fma(z * z, pc, fma(z, -0.5, 1.0));
+  const int q = (int)n;
+  const bool swap = (q & 1) != 0;
+  const double s0 = swap ? c_r : s_r, c0 = swap ? s_r : c_r;
+  // sin changes sign in quadrants 2, 3; cos in quadrants 1, 2
+  const uint64_t ss = (uint64_t)(q & 2) << 62, cc = (uint64_t)((q + 1) & 2) << 62;
+  sn = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, s0) ^ ss);
+  cs = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, c0) ^ cc);
+}
+__device__ __forceinline__ float exp_neg_t(float y) { return __expf(-y); }
 
 // Far-field cut-offs.  Screening: for alpha*rho > kScreenFar the terms of
 // dZ e^{-alpha rho} in V, V' and V'' are below 1e-21 of the Z_inf terms, far
@@ -36,17 +141,27 @@ template <> struct PotConst<double> {
   __device__ static double dZ(const Desc& d, int c) { return d.dZ[c]; }
   __device__ static double alpha(const Desc& d, int c) { return d.alpha[c]; }
   __device__ static double eps2(const Desc& d, int c) { return d.eps2[c]; }
+  __device__ static double adZ(const Desc& d, int c) { return d.adZ[c]; }
+  __device__ static double a2dZ(const Desc& d, int c) { return d.a2dZ[c]; }
 };
 template <> struct PotConst<float> {
   __device__ static float Zinf(const Desc& d, int c) { return d.fZinf[c]; }
   __device__ static float dZ(const Desc& d, int c) { return d.fdZ[c]; }
   __device__ static float alpha(const Desc& d, int c) { return d.falpha[c]; }
   __device__ static float eps2(const Desc& d, int c) { return d.feps2[c]; }
+  __device__ static float adZ(const Desc& d, int c) { return d.fadZ[c]; }
+  __device__ static float a2dZ(const Desc& d, int c) { return d.fa2dZ[c]; }
 };
 
 // Two-centre potential of Eq. 7 with softened distance (per centre
-// V_i = -Z_i(rho)/rho, Z_i = Zinf + dZ e^{-alpha rho}, rho^2 = |q-R_i|^2 + eps2):
-// value, gradient and the symmetric Hessian K (xx, yy, zz, xy, xz, yz).
+// V_i = -Z_i(rho)/rho, Z_i = Zinf + dZ u, u = e^{-alpha rho},
+// rho^2 = |q-R_i|^2 + eps2): value, gradient and the symmetric Hessian K
+// (xx, yy, zz, xy, xz, yz).  With s = 1/rho and A = alpha dZ:
+//   V_i' = s t,  t = Z s + A u,
+//   V_i'' = -2 Z s^3 - 2 A u s^2 - alpha A u s,
+// so that grad V_i = s^2 t d and
+//   Hess V_i = s^2 t I + c2 d d^T,  c2 = (V_i'' - V_i'/rho) s^2
+//                                      = -s^3 (3 s t + alpha A u).
 template <typename T>
 __device__ __forceinline__ void potential(const Desc& d, const T hRn[3], const T q[3], T& V,
                                           T g[3], T K[6]) {
@@ -55,39 +170,40 @@ __device__ __forceinline__ void potential(const Desc& d, const T hRn[3], const T
   g[0] = g[1] = g[2] = T(0);
 #pragma unroll
   for (int a = 0; a < 6; ++a) K[a] = T(0);
+  T diag = T(0);
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     const T dx = c == 0 ? q[0] - hRn[0] : q[0] + hRn[0];
     const T dy = c == 0 ? q[1] - hRn[1] : q[1] + hRn[1];
     const T dz = c == 0 ? q[2] - hRn[2] : q[2] + hRn[2];
     const T r2 = dx * dx + dy * dy + dz * dz + PC::eps2(d, c);
-    const T inv = rsqrt_t(r2);
-    T Z = PC::Zinf(d, c);
-    T f1 = Z * inv * inv;
-    T f2 = T(-2) * Z * inv * inv * inv;
+    const T s = rsqrt_t(r2);
+    T u = T(0);
     if (d.screened) {
-      const T ar = PC::alpha(d, c) * (r2 * inv);
-      if (ar < T(kScreenFar)) {
-        const T ex = exp_t(-ar);
-        const T adx = PC::alpha(d, c) * PC::dZ(d, c) * ex;
-        Z += PC::dZ(d, c) * ex;
-        f1 = (Z * inv + adx) * inv;
-        f2 = -(T(2) * Z * inv * inv + T(2) * adx * inv + PC::alpha(d, c) * adx) * inv;
-      }
+      const T ar = PC::alpha(d, c) * (r2 * s);
+      if (ar < T(kScreenFar)) u = exp_neg_t(ar);
     }
-    V -= Z * inv;
-    const T c1 = f1 * inv;               // f'/rho
-    const T c2 = (f2 - c1) * inv * inv;  // (f'' - f'/rho)/rho^2
+    const T Z = PC::Zinf(d, c) + PC::dZ(d, c) * u;
+    const T t = Z * s + PC::adZ(d, c) * u;
+    const T s2 = s * s;
+    const T c1 = s2 * t;  // V_i'/rho
+    const T c2 = -(s2 * s) * (T(3) * s * t + PC::a2dZ(d, c) * u);
+    V -= Z * s;
     g[0] += c1 * dx;
     g[1] += c1 * dy;
     g[2] += c1 * dz;
-    K[0] += c2 * dx * dx + c1;
-    K[1] += c2 * dy * dy + c1;
-    K[2] += c2 * dz * dz + c1;
-    K[3] += c2 * dx * dy;
-    K[4] += c2 * dx * dz;
-    K[5] += c2 * dy * dz;
+    diag += c1;
+    const T ex = c2 * dx, ey = c2 * dy;
+    K[0] += ex * dx;
+    K[1] += ey * dy;
+    K[2] += c2 * dz * dz;
+    K[3] += ex * dy;
+    K[4] += ex * dz;
+    K[5] += ey * dz;
   }
+  K[0] += diag;
+  K[1] += diag;
+  K[2] += diag;
 }
 
 // y = K x for the symmetric 3x3 K
@@ -265,66 +381,68 @@ __device__ __forceinline__ void prefactor_step(const double Rr[3][3], const doub
 
 // Re a_k of the amplitude a = -w C e^{i Phi} <psi0|k_z|p,q>,
 // Phi = S - Ip (t_k - t0) + p0.q0 (Sec. II.A; Eq. 4), with the recombination
-// element as a sum of Gaussian moments of the GTO primitives.  Primitives
-// below the far-field cut are skipped (their terms are < 1e-30).
+// element as a sum of Gaussian moments of the GTO primitives, taken shell by
+// shell (the primitives of one centre and exponent share the Gaussian
+// factor).  Shells below the far-field cut are skipped (their terms are
+// < 1e-30).
 __device__ __forceinline__ double amplitude_re(const Desc& d, const double n[3],
                                                const double p[3], const double q[3],
                                                double Cre, double Cim, double S, double tk,
                                                double t0, double p0q0, double w) {
   const double pp = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
-  const double np_ = n[0] * p[0] + n[1] * p[1] + n[2] * p[2];
-  double dd[2], pd[2], nd[2], dz[2];
+  double dd[2];
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     const double s = c == 0 ? d.half_R : -d.half_R;
     const double x = s * n[0] - q[0], y = s * n[1] - q[1], z = s * n[2] - q[2];
     dd[c] = x * x + y * y + z * z;
-    pd[c] = p[0] * x + p[1] * y + p[2] * z;
-    nd[c] = n[0] * x + n[1] * y + n[2] * z;
-    dz[c] = z;
   }
   // ln(1 + |C|) bound from the binary exponent of 1 + |C|^2
   const double cc = 1.0 + Cre * Cre + Cim * Cim;
   const double lnC = 0.3466 * (double)(((int)(__double_as_longlong(cc) >> 52) & 0x7ff) - 1022);
-  // every primitive's exponent er <= -|R_a - q|^2 / (4 kappa2) <= -dd g_inv4k_min
+  // every shell's exponent er <= -|R_a - q|^2 / (4 kappa2) <= -dd g_inv4k_min
   // (the |p|^2 coefficient of er is <= 0): the whole sum is below the cut
   if (fmin(dd[0], dd[1]) * d.g_inv4k_min + kRecombFar > lnC) return 0.0;
+  const double np_ = n[0] * p[0] + n[1] * p[1] + n[2] * p[2];
   const double bzr = p[2] * d.inv_gamma;
+  const double nbr = np_ * d.inv_gamma;
   const double bb_re_p = pp * d.inv_gamma2;
+  const double ppg = pp * d.half_inv_gamma;
   double rr = 0.0, ri = 0.0;
-  for (int j = 0; j < d.n_gto; ++j) {
-    const int c = (d.g_l[j] >> 1) & 1;
-    const double ddc = c == 0 ? dd[0] : dd[1];
-    const double pdc = c == 0 ? pd[0] : pd[1];
-    const double dzc = c == 0 ? dz[0] : dz[1];
-    const double i4 = d.g_inv4k[j], i2 = d.g_inv2k[j];
-    const double er = (bb_re_p - ddc) * i4 - pp * d.half_inv_gamma;
-    if (er + lnC < kRecombFar) continue;
-    const double ei = 2.0 * pdc * d.inv_gamma * i4;
-    const double gm = d.g_norm[j] * exp(er);
-    double sn, cs;
-    sincos(ei, &sn, &cs);
-    const double Gr = gm * cs, Gi = gm * sn;
-    double Xr, Xi;
-    if ((d.g_l[j] & 1) == 0) {
-      Xr = bzr * i2;
-      Xi = dzc * i2;
-    } else {
-      const double ndc = c == 0 ? nd[0] : nd[1];
-      const double nbr = np_ * d.inv_gamma, nbi = ndc;
-      // i/(2a) [n_z/(2k) + b_z (n.b)/(4k^2)]
-      const double ur = n[2] * i2 + (bzr * nbr - dzc * nbi) * i2 * i2;
-      const double ui = (bzr * nbi + dzc * nbr) * i2 * i2;
-      Xr = -ui * d.g_i2a[j];
-      Xi = ur * d.g_i2a[j];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const double s = c == 0 ? d.half_R : -d.half_R;
+    const double x = s * n[0] - q[0], y = s * n[1] - q[1], dz = s * n[2] - q[2];
+    const double pd = p[0] * x + p[1] * y + p[2] * dz;  // p.(R_a - q)
+    const double nd = n[0] * x + n[1] * y + n[2] * dz;  // n.(R_a - q)
+    const double ddc = dd[c];
+    const int j0 = c == 0 ? 0 : d.n_shell0, j1 = c == 0 ? d.n_shell0 : d.n_shell;
+    for (int j = j0; j < j1; ++j) {
+      const double i4 = d.sh_inv4k[j], i2 = 2.0 * i4;
+      const double er = (bb_re_p - ddc) * i4 - ppg;  // <= 0
+      if (er + lnC < kRecombFar) continue;
+      const double ei = 2.0 * pd * d.inv_gamma * i4;
+      const double gm = exp_neg(-er);
+      double sn, cs;
+      sincos_k(ei, sn, cs);
+      const double Gr = gm * cs, Gi = gm * sn;
+      // s primitives: b_z / (2 kappa2); p primitives:
+      // i/(2a) [n_z/(2 kappa2) + b_z (n.b)/(4 kappa2^2)], b = p/gamma + i (R_a - q)
+      double Xr = d.sh_ns[j] * bzr * i2, Xi = d.sh_ns[j] * dz * i2;
+      if (d.sh_np[j] != 0.0) {
+        const double ur = n[2] * i2 + (bzr * nbr - dz * nd) * i2 * i2;
+        const double ui = (bzr * nd + dz * nbr) * i2 * i2;
+        Xr -= d.sh_np[j] * ui;
+        Xi += d.sh_np[j] * ur;
+      }
+      rr += Gr * Xr - Gi * Xi;
+      ri += Gr * Xi + Gi * Xr;
     }
-    rr += Gr * Xr - Gi * Xi;
-    ri += Gr * Xi + Gi * Xr;
   }
   if (rr == 0.0 && ri == 0.0) return 0.0;
   const double phi = S - d.Ip * (tk - t0) + p0q0;
   double sp, cp;
-  sincos(phi, &sp, &cp);
+  sincos_k(phi, sp, cp);
   const double er_ = Cre * cp - Cim * sp, ei_ = Cre * sp + Cim * cp;
   return -w * (er_ * rr - ei_ * ri);
 }

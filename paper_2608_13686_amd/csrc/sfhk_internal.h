@@ -22,7 +22,9 @@ struct Desc {
   // target (Eq. 7) and coherent state
   double half_R, Ip, gamma, inv_gamma, inv_gamma2, half_inv_gamma;
   double Zinf[2], dZ[2], alpha[2], eps2[2];
+  double adZ[2], a2dZ[2];  // alpha dZ and alpha^2 dZ
   float fZinf[2], fdZ[2], falpha[2], feps2[2];  // the same, rounded to FP32
+  float fadZ[2], fa2dZ[2];
   // sampling (first-order tunnel exit and amplitude weight)
   double sigma, w_cut, kappa, wpow, kcube3, inv_E0;
   double nfix[3];
@@ -31,13 +33,21 @@ struct Desc {
   uint64_t field_off;  // doubles: E(t_k) at 2k, E(t_k + dt/2) at 2k + 1
   uint64_t acc_off;    // accum / histogram bin of step 0
   uint64_t slot_off, n_slots;
-  // GTO primitives: l | centre << 1 (centre 0 at +R/2 n), 1/(4 kappa2),
-  // 1/(2 kappa2), the recombination normalisation, 1/(2a) and c (2a)^{-3/2},
-  // with kappa2 = 1/(4a) + 1/(2 gamma)
-  double g_ion[SFHK_MAX_GTO], g_inv4k[SFHK_MAX_GTO], g_inv2k[SFHK_MAX_GTO];
-  double g_norm[SFHK_MAX_GTO], g_i2a[SFHK_MAX_GTO];
+  // GTO primitives (ionisation matrix element): l | centre << 1 (centre 0
+  // at +R/2 n), 1/(2a) and c (2a)^{-3/2}
+  double g_ion[SFHK_MAX_GTO], g_i2a[SFHK_MAX_GTO];
   int32_t g_l[SFHK_MAX_GTO];
-  double g_inv4k_min;  // smallest 1/(4 kappa2) over the primitives
+  // Recombination shells: the primitives of one centre and one exponent a
+  // share the Gaussian factor of the recombination element.  Shells of
+  // centre 0 come first (n_shell0 of them).  Per shell: 1/(4 kappa2) with
+  // kappa2 = 1/(4a) + 1/(2 gamma) (half of 1/(2 kappa2)), and the summed
+  // normalisations of its s primitives and of its p primitives (the latter
+  // times 1/(2a)); a normalisation is c (2a)^{-3/2} (pi gamma)^{-3/4}
+  // (pi/kappa2)^{3/2}.
+  int32_t n_shell, n_shell0;
+  double sh_inv4k[SFHK_MAX_GTO];
+  double sh_ns[SFHK_MAX_GTO], sh_np[SFHK_MAX_GTO];
+  double g_inv4k_min;  // smallest 1/(4 kappa2) over the shells
   double c_max2;       // prefactor cap squared (0: none)
 };
 

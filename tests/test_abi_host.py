@@ -105,6 +105,10 @@ def test_bad_gto_and_alignment_rejected(L):
     arr = _abi.make_problems([p])
     arr[0].tgt.n_gto = 0
     assert L.lib().sfhk_problem_steps(arr, None, None, None) == 1
+    for key in ("alpha", "eps2"):  # a growing screening, an imaginary softening
+        p = workloads.n2()
+        p["target"]["centers"][1][key] = -1.0
+        assert L.lib().sfhk_problem_steps(_abi.make_problems([p]), None, None, None) == 1
 
 
 def test_entry_points_validate_before_enqueueing(L):
