@@ -295,6 +295,49 @@ __device__ __forceinline__ void apply_step_matrix(const StepMatrix<T>& P, const 
   }
 }
 
+// M <- P M for the monodromy held in LDS (element-major, lane-minor: row-major
+// 6x6, rows (q, p), columns (q0, p0)), one column at a time, and R =
+// 1/2 (Mqq + Mpp - i g Mqp + (i/g) Mpq) rebuilt from the new columns
+// (column c < 3 holds Mqq[:, c] and Mpq[:, c], column c + 3 holds Mqp[:, c]
+// and Mpp[:, c]).  The next column is loaded before the current one is
+// computed, so that the LDS latency is hidden behind its arithmetic; the
+// scheduling barrier per column bounds the registers in flight.
+template <int W>
+__device__ __forceinline__ void monodromy_step(const StepMatrix<double>& P, double (*mono)[W],
+                                               int lane, double gamma, double inv_gamma,
+                                               double Rr[3][3], double Ri[3][3]) {
+  double x[3] = {mono[0][lane], mono[6][lane], mono[12][lane]};
+  double v[3] = {mono[18][lane], mono[24][lane], mono[30][lane]};
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    __builtin_amdgcn_sched_barrier(0);
+    double xl[3] = {0.0, 0.0, 0.0}, vl[3] = {0.0, 0.0, 0.0};
+    if (c < 5) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        xl[r] = mono[6 * r + c + 1][lane];
+        vl[r] = mono[18 + 6 * r + c + 1][lane];
+      }
+    }
+    double xn[3], vn[3];
+    apply_step_matrix(P, x, v, xn, vn);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      mono[6 * r + c][lane] = xn[r];
+      mono[18 + 6 * r + c][lane] = vn[r];
+      if (c < 3) {
+        Rr[r][c] = 0.5 * xn[r];
+        Ri[r][c] = 0.5 * inv_gamma * vn[r];
+      } else {
+        Rr[r][c - 3] += 0.5 * vn[r];
+        Ri[r][c - 3] -= 0.5 * gamma * xn[r];
+      }
+      x[r] = xl[r];
+      v[r] = vl[r];
+    }
+  }
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);

@@ -151,26 +151,7 @@ __device__ __forceinline__ void run_pack(const Desc* __restrict__ descs,
     // columns c and c + 3 give column c of R.
     StepMatrix<double> P;
     rk4_step_matrix(K1, K2, K3, K4, h, P);
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      __builtin_amdgcn_sched_barrier(0);
-      const double x0[3] = {mono[c][lane], mono[6 + c][lane], mono[12 + c][lane]};
-      const double v0[3] = {mono[18 + c][lane], mono[24 + c][lane], mono[30 + c][lane]};
-      double xn[3], vn[3];
-      apply_step_matrix(P, x0, v0, xn, vn);
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        mono[6 * r + c][lane] = xn[r];
-        mono[18 + 6 * r + c][lane] = vn[r];
-        if (c < 3) {  // x = Mqq[:, c], v = Mpq[:, c]
-          Rr[r][c] = 0.5 * xn[r];
-          Ri[r][c] = 0.5 * d.inv_gamma * vn[r];
-        } else {      // x = Mqp[:, c-3], v = Mpp[:, c-3]
-          Rr[r][c - 3] += 0.5 * vn[r];
-          Ri[r][c - 3] -= 0.5 * d.gamma * xn[r];
-        }
-      }
-    }
+    monodromy_step(P, mono, lane, d.gamma, d.inv_gamma, Rr, Ri);
   }
   }
 

@@ -169,26 +169,7 @@ serve_slice_f64(const ReqDev* __restrict__ reqs, SliceTable tab) {
     }
     StepMatrix<double> P;
     rk4_step_matrix(K1, K2, K3, K4, h, P);
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      __builtin_amdgcn_sched_barrier(0);
-      const double x0[3] = {mono[c][lane], mono[6 + c][lane], mono[12 + c][lane]};
-      const double v0[3] = {mono[18 + c][lane], mono[24 + c][lane], mono[30 + c][lane]};
-      double xn[3], vn[3];
-      apply_step_matrix(P, x0, v0, xn, vn);
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        mono[6 * r + c][lane] = xn[r];
-        mono[18 + 6 * r + c][lane] = vn[r];
-        if (c < 3) {
-          Rr[r][c] = 0.5 * xn[r];
-          Ri[r][c] = 0.5 * d.inv_gamma * vn[r];
-        } else {
-          Rr[r][c - 3] += 0.5 * vn[r];
-          Ri[r][c - 3] -= 0.5 * d.gamma * xn[r];
-        }
-      }
-    }
+    monodromy_step(P, mono, lane, d.gamma, d.inv_gamma, Rr, Ri);
   }
   // flush the partial 64-step block of dipole sums left at the window end
   if (acc_reg != 0.0) unsafeAtomicAdd(&acc[((k - 1) & ~(kWave - 1)) + lane], acc_reg);
