@@ -34,40 +34,48 @@ __device__ __forceinline__ double sconst() {
   asm volatile("s_mov_b32 %0, %1" : "=s"(hi) : "i"((uint32_t)(B >> 32)));
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
-// a b + C
-template <uint64_t C>
-__device__ __forceinline__ double fma_k(double a, double b) {
+// VOP3 arithmetic with one operand k held in an SGPR pair.
+__device__ __forceinline__ double fma_s(double a, double b, double k) {  // a b + k
   double d;
-  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(sconst<C>()));
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(k));
   return d;
 }
-// c - a C
-template <uint64_t C>
-__device__ __forceinline__ double fnma_k(double a, double c) {
+__device__ __forceinline__ double fnma_s(double a, double k, double c) {  // c - a k
   double d;
-  asm("v_fma_f64 %0, -%1, %2, %3" : "=v"(d) : "v"(a), "s"(sconst<C>()), "v"(c));
+  asm("v_fma_f64 %0, -%1, %2, %3" : "=v"(d) : "v"(a), "s"(k), "v"(c));
   return d;
 }
-// a C
-template <uint64_t C>
-__device__ __forceinline__ double mul_k(double a) {
+__device__ __forceinline__ double fnms_s(double a, double k, double b) {  // -a k - b
   double d;
-  asm("v_mul_f64 %0, %1, %2" : "=v"(d) : "v"(a), "s"(sconst<C>()));
+  asm("v_fma_f64 %0, -%1, %2, -%3" : "=v"(d) : "v"(a), "s"(k), "v"(b));
   return d;
 }
-// a + C
-template <uint64_t C>
-__device__ __forceinline__ double add_k(double a) {
+__device__ __forceinline__ double mul_s(double a, double k) {
   double d;
-  asm("v_add_f64 %0, %1, %2" : "=v"(d) : "v"(a), "s"(sconst<C>()));
+  asm("v_mul_f64 %0, %1, %2" : "=v"(d) : "v"(a), "s"(k));
   return d;
 }
-// -a C - b
-template <uint64_t C>
-__device__ __forceinline__ double fnms_k(double a, double b) {
+__device__ __forceinline__ double add_s(double a, double k) {
   double d;
-  asm("v_fma_f64 %0, -%1, %2, -%3" : "=v"(d) : "v"(a), "s"(sconst<C>()), "v"(b));
+  asm("v_add_f64 %0, %1, %2" : "=v"(d) : "v"(a), "s"(k));
   return d;
+}
+template <uint64_t C>
+__device__ __forceinline__ double fma_k(double a, double b) { return fma_s(a, b, sconst<C>()); }
+template <uint64_t C>
+__device__ __forceinline__ double fnma_k(double a, double c) { return fnma_s(a, sconst<C>(), c); }
+template <uint64_t C>
+__device__ __forceinline__ double fnms_k(double a, double b) { return fnms_s(a, sconst<C>(), b); }
+template <uint64_t C>
+__device__ __forceinline__ double mul_k(double a) { return mul_s(a, sconst<C>()); }
+template <uint64_t C>
+__device__ __forceinline__ double add_k(double a) { return add_s(a, sconst<C>()); }
+// one Horner step q <- q r + C of two independent evaluations sharing C
+template <uint64_t C>
+__device__ __forceinline__ void horner2(double& q0, double& q1, double r0, double r1) {
+  const double k = sconst<C>();
+  q0 = fma_s(q0, r0, k);
+  q1 = fma_s(q1, r1, k);
 }
 
 // e^{-y} for 0 <= y <= 708.  -y = n ln2 + r with n = rint(-y / ln2) and
@@ -75,6 +83,36 @@ __device__ __forceinline__ double fnms_k(double a, double b) {
 // ln2 corrects the rest); e^r = 1 + r (1 + r q(r)) with q a degree-9
 // Chebyshev fit of (e^r - 1 - r) / r^2 on |r| <= ln2/2; 2^n by ldexp.
 // Error < 0.7 ulp for results in the normal range; no range checks.
+// exp_neg2 evaluates two arguments in lock step (shared constants,
+// interleaved dependency chains).
+__device__ __forceinline__ void exp_neg2(double y0, double y1, double& e0, double& e1) {
+  double k = sconst<dbits(-1.4426950408889634)>();
+  const double n0 = __builtin_rint(mul_s(y0, k)), n1 = __builtin_rint(mul_s(y1, k));
+  k = sconst<dbits(0.6931471805599453)>();
+  double r0 = fnms_s(n0, k, y0), r1 = fnms_s(n1, k, y1);
+  k = sconst<dbits(2.3190468138462996e-17)>();
+  r0 = fnma_s(n0, k, r0);
+  r1 = fnma_s(n1, k, r1);
+  k = sconst<dbits(2.5100375832561234e-08)>();
+  double q0 = mul_s(r0, k), q1 = mul_s(r1, k);
+  k = sconst<dbits(2.7620075879983367e-07)>();
+  q0 = add_s(q0, k);
+  q1 = add_s(q1, k);
+  horner2<dbits(2.7557268480310024e-06)>(q0, q1, r0, r1);
+  horner2<dbits(2.4801521322368692e-05)>(q0, q1, r0, r1);
+  horner2<dbits(0.00019841269863040545)>(q0, q1, r0, r1);
+  horner2<dbits(0.0013888888917196719)>(q0, q1, r0, r1);
+  horner2<dbits(0.008333333333330065)>(q0, q1, r0, r1);
+  horner2<dbits(0.041666666666624164)>(q0, q1, r0, r1);
+  horner2<dbits(0.16666666666666669)>(q0, q1, r0, r1);
+  horner2<dbits(0.5000000000000001)>(q0, q1, r0, r1);
+  q0 = fma(q0, r0, 1.0);
+  q1 = fma(q1, r1, 1.0);
+  q0 = fma(q0, r0, 1.0);
+  q1 = fma(q1, r1, 1.0);
+  e0 = __builtin_amdgcn_ldexp(q0, (int)n0);
+  e1 = __builtin_amdgcn_ldexp(q1, (int)n1);
+}
 __device__ __forceinline__ double exp_neg(double y) {
   const double n = __builtin_rint(mul_k<dbits(-1.4426950408889634)>(y));
   double r = fnms_k<dbits(0.6931471805599453)>(n, y);
@@ -92,7 +130,9 @@ __device__ __forceinline__ double exp_neg(double y) {
   q = fma(q, r, 1.0);
   return __builtin_amdgcn_ldexp(q, (int)n);
 }
-__device__ __forceinline__ double exp_neg_t(double y) { return exp_neg(y); }
+__device__ __forceinline__ void exp_neg2_t(double y0, double y1, double& e0, double& e1) {
+  exp_neg2(y0, y1, e0, e1);
+}
 
 // sin x and cos x for |x| < 2^31.  x = n pi/2 + r with n = rint(2x/pi) and
 // |r| <= pi/4 (pi/2 in two parts; the first FMA is exact); on |r| <= pi/4,
@@ -124,15 +164,21 @@ __device__ __forceinline__ void sincos_k(double x, double& sn, double& cs) {
   sn = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, s0) ^ ss);
   cs = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, c0) ^ cc);
 }
-__device__ __forceinline__ float exp_neg_t(float y) { return __expf(-y); }
+__device__ __forceinline__ void exp_neg2_t(float y0, float y1, float& e0, float& e1) {
+  e0 = __expf(-y0);
+  e1 = __expf(-y1);
+}
 
-// Far-field cut-offs.  Screening: for alpha*rho > kScreenFar the terms of
-// dZ e^{-alpha rho} in V, V' and V'' are below 1e-21 of the Z_inf terms, far
-// under one rounding unit, so they are not evaluated.  Recombination: a GTO
+// Far-field cut-offs.  Screening: for alpha*rho > kScreenFar at both centres
+// the terms of dZ e^{-alpha rho} in V, V' and V'' are below 1e-21 of the
+// Z_inf terms, far under one rounding unit, so they are not evaluated; when
+// they are, the exponent is capped at kScreenCap (e^{-700} is nothing next to
+// Z_inf, and the cap keeps the exponential in its range).  Recombination: a GTO
 // primitive whose Gaussian exponent satisfies er + ln(1 + |C|) < kRecombFar
 // contributes less than 1e-30 to a dipole sample (|b|-dependent factors and
 // norms are bounded by 1e4), so its exp and sincos are not evaluated.
 constexpr double kScreenFar = 60.0;
+constexpr double kScreenCap = 700.0;
 constexpr double kRecombFar = -75.0;
 
 template <typename T> struct PotConst;
@@ -166,6 +212,23 @@ template <typename T>
 __device__ __forceinline__ void potential(const Desc& d, const T hRn[3], const T q[3], T& V,
                                           T g[3], T K[6]) {
   using PC = PotConst<T>;
+  T dx[2], dy[2], dz[2], r2[2], s[2], u[2] = {T(0), T(0)};
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    dx[c] = c == 0 ? q[0] - hRn[0] : q[0] + hRn[0];
+    dy[c] = c == 0 ? q[1] - hRn[1] : q[1] + hRn[1];
+    dz[c] = c == 0 ? q[2] - hRn[2] : q[2] + hRn[2];
+    r2[c] = dx[c] * dx[c] + dy[c] * dy[c] + dz[c] * dz[c] + PC::eps2(d, c);
+    s[c] = rsqrt_t(r2[c]);
+  }
+  if (d.screened) {
+    // both centres' screening factors at once (an electron far from one
+    // centre is far from the other); the argument is capped where e^{-y}
+    // is far below a rounding unit of Z_inf
+    const T ar0 = PC::alpha(d, 0) * (r2[0] * s[0]), ar1 = PC::alpha(d, 1) * (r2[1] * s[1]);
+    if (ar0 < T(kScreenFar) || ar1 < T(kScreenFar))
+      exp_neg2_t(fmin(ar0, T(kScreenCap)), fmin(ar1, T(kScreenCap)), u[0], u[1]);
+  }
   V = T(0);
   g[0] = g[1] = g[2] = T(0);
 #pragma unroll
@@ -173,33 +236,23 @@ __device__ __forceinline__ void potential(const Desc& d, const T hRn[3], const T
   T diag = T(0);
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    const T dx = c == 0 ? q[0] - hRn[0] : q[0] + hRn[0];
-    const T dy = c == 0 ? q[1] - hRn[1] : q[1] + hRn[1];
-    const T dz = c == 0 ? q[2] - hRn[2] : q[2] + hRn[2];
-    const T r2 = dx * dx + dy * dy + dz * dz + PC::eps2(d, c);
-    const T s = rsqrt_t(r2);
-    T u = T(0);
-    if (d.screened) {
-      const T ar = PC::alpha(d, c) * (r2 * s);
-      if (ar < T(kScreenFar)) u = exp_neg_t(ar);
-    }
-    const T Z = PC::Zinf(d, c) + PC::dZ(d, c) * u;
-    const T t = Z * s + PC::adZ(d, c) * u;
-    const T s2 = s * s;
+    const T Z = PC::Zinf(d, c) + PC::dZ(d, c) * u[c];
+    const T t = Z * s[c] + PC::adZ(d, c) * u[c];
+    const T s2 = s[c] * s[c];
     const T c1 = s2 * t;  // V_i'/rho
-    const T c2 = -(s2 * s) * (T(3) * s * t + PC::a2dZ(d, c) * u);
-    V -= Z * s;
-    g[0] += c1 * dx;
-    g[1] += c1 * dy;
-    g[2] += c1 * dz;
+    const T c2 = -(s2 * s[c]) * (T(3) * s[c] * t + PC::a2dZ(d, c) * u[c]);
+    V -= Z * s[c];
+    g[0] += c1 * dx[c];
+    g[1] += c1 * dy[c];
+    g[2] += c1 * dz[c];
     diag += c1;
-    const T ex = c2 * dx, ey = c2 * dy;
-    K[0] += ex * dx;
-    K[1] += ey * dy;
-    K[2] += c2 * dz * dz;
-    K[3] += ex * dy;
-    K[4] += ex * dz;
-    K[5] += ey * dz;
+    const T ex = c2 * dx[c], ey = c2 * dy[c];
+    K[0] += ex * dx[c];
+    K[1] += ey * dy[c];
+    K[2] += c2 * dz[c] * dz[c];
+    K[3] += ex * dy[c];
+    K[4] += ex * dz[c];
+    K[5] += ey * dz[c];
   }
   K[0] += diag;
   K[1] += diag;
