@@ -296,23 +296,23 @@ def averaging_variant(sf, sizes=(1 << 14, 1 << 16, 1 << 18, 1 << 20), reps=3,
             "rows": rows, "seconds": time.perf_counter() - t}
 
 
-def served_variant(sf, n_req, rate_hz, window=1024, h_max=100.0, h_step=0.1, n_groups=2):
-    """p50/p99 latency and spectra/s of a seeded Poisson request stream under
-    continuous batching (processor sharing and shortest-remaining-work) and
-    under a FIFO server on the plain FP64 path."""
+def served_variant(sf, n_req, rates, window=1024, h_max=100.0, h_step=0.1, n_groups=2):
+    """p50/p99 latency and spectra/s of seeded Poisson request streams (one
+    per arrival rate) under continuous batching (processor sharing and
+    shortest-remaining-work) and under a FIFO server on the plain FP64 path.
+    One executor (one pool, one set of streams) serves every stream."""
     import torch
     from paper_2608_13686_amd.serve import (HipExecutor, Server, fifo_stream, latency_stats,
                                             plain_fp64_runner, serve_stream)
-    stream = workloads.request_stream(n_req, rate_hz)
     n_omega = int(round(h_max / h_step)) + 1
     pool = 48 << 30
     x = HipExecutor(pool, 64, n_omega, h_step, n_groups=n_groups)
     # untimed warm-up: one small request through every kernel
+    warm_prob = workloads.request_stream(1, rates[0])[0][1]
     warm = Server(x, pool, max_requests=64, window=window)
-    warm.submit("warm", stream[0][1], 4096, 1)
+    warm.submit("warm", warm_prob, 4096, 1)
     warm.drain()
-    fifo_warm = plain_fp64_runner(h_max, h_step)
-    fifo_warm(stream[0][1], 4096, 1)
+    plain_fp64_runner(h_max, h_step)(warm_prob, 4096, 1)
     torch.cuda.synchronize()
 
     def summary(done, t_first, wall):
@@ -322,26 +322,31 @@ def served_variant(sf, n_req, rate_hz, window=1024, h_max=100.0, h_step=0.1, n_g
                 "mean_s": st["mean_s"], "max_s": st["max_s"], "spectra_per_s": len(done) / span,
                 "wall_s": wall}
 
-    res = {"workload": f"poisson-{n_req}req-{rate_hz:g}hz-seed1004", "n_requests": n_req,
-           "rate_hz": rate_hz, "window_steps": window, "pack_groups": n_groups,
-           "n_omega": n_omega,
-           "trajectories_total": int(sum(n for _, _, n, _ in stream)),
-           "precision": "fp64"}
-    for policy in ("ps", "srpt"):
-        S = Server(x, pool, max_requests=64, window=window, policy=policy)
+    out = []
+    for rate_hz in rates:
+        stream = workloads.request_stream(n_req, rate_hz)
+        res = {"workload": f"poisson-{n_req}req-{rate_hz:g}hz-seed1004", "n_requests": n_req,
+               "rate_hz": rate_hz, "window_steps": window, "pack_groups": n_groups,
+               "n_omega": n_omega,
+               "trajectories_total": int(sum(n for _, _, n, _ in stream)),
+               "precision": "fp64"}
+        for policy in ("ps", "srpt"):
+            S = Server(x, pool, max_requests=64, window=window, policy=policy)
+            t = time.perf_counter()
+            done = serve_stream(S, stream)
+            wall = time.perf_counter() - t
+            res[f"served_{policy}"] = summary(done, t, wall)
+            res[f"served_{policy}"]["peak_pool_bytes"] = S.peak_bytes
+            res[f"served_{policy}"]["peak_concurrent"] = S.peak_active
+            print(f"served ({policy}, {rate_hz:g}/s): {res[f'served_{policy}']}", file=sys.stderr,
+                  flush=True)
         t = time.perf_counter()
-        done = serve_stream(S, stream)
+        done = fifo_stream(stream, plain_fp64_runner(h_max, h_step))
         wall = time.perf_counter() - t
-        res[f"served_{policy}"] = summary(done, t, wall)
-        res[f"served_{policy}"]["peak_pool_bytes"] = S.peak_bytes
-        res[f"served_{policy}"]["peak_concurrent"] = S.peak_active
-        print(f"served ({policy}): {res[f'served_{policy}']}", file=sys.stderr, flush=True)
-    t = time.perf_counter()
-    done = fifo_stream(stream, plain_fp64_runner(h_max, h_step))
-    wall = time.perf_counter() - t
-    res["fifo_fp64"] = summary(done, t, wall)
-    print(f"fifo: {res['fifo_fp64']}", file=sys.stderr, flush=True)
-    return res
+        res["fifo_fp64"] = summary(done, t, wall)
+        print(f"fifo ({rate_hz:g}/s): {res['fifo_fp64']}", file=sys.stderr, flush=True)
+        out.append(res)
+    return out
 
 
 def main():
@@ -356,7 +361,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="measure only the headline FP64 workload")
     ap.add_argument("--serve-requests", type=int, default=120)
-    ap.add_argument("--serve-rate", type=float, default=12.0, help="Poisson arrivals per second")
+    ap.add_argument("--serve-rate", default="12,14",
+                    help="Poisson arrivals per second; a comma list runs one stream per rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path shards by trajectory index with one "
@@ -524,7 +530,9 @@ def main():
         print(f"averaging: {variants['averaging']}", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         if args.serve_requests > 0:
-            variants["served"] = served_variant(sf, args.serve_requests, args.serve_rate)
+            rates = [float(r) for r in str(args.serve_rate).split(",") if r]
+            for i, res in enumerate(served_variant(sf, args.serve_requests, rates)):
+                variants["served" if i == 0 else f"served_{rates[i]:g}hz"] = res
         out["variants"] = variants
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(probs, seeds)
