@@ -92,9 +92,48 @@ def cpu_baseline(probs, seeds, budget_s=12.0):
         if el > budget_s / 4 or n >= 65536:
             break
         n = min(65536, int(n * max(2.0, budget_s / max(el, 1e-3) / 1.5)))
+    # the whole small H2 workload (4,096 trajectories), as a latency reference
+    h2 = workloads.h2_softcore()
+    t = time.perf_counter()
+    _, h2_steps, _ = oracle.run(h2, 1001, 0, 4096, cores)
+    h2_s = time.perf_counter() - t
     return {"value": steps / el, "unit": "trajectory-steps/s", "cores": cores, "kind": "oracle",
             "sample": f"trajectories 0..{n - 1} of each of the {len(probs)} problems "
-                      f"({steps} live trajectory-steps, {el:.2f} s)"}
+                      f"({steps} live trajectory-steps, {el:.2f} s)",
+            "cpu_model": cpu_model(),
+            "h2_4096_whole_workload_s": h2_s, "h2_4096_live_trajectory_steps": int(h2_steps)}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def small_variant(sf, reps=5):
+    """The small H2 workload (4,096 trajectories, 3,310 steps, harmonics to
+    40) end to end: sampling, packing, propagation, dipole and spectrum.  At
+    64 wavefronts on 1,024 SIMDs it measures latency, not throughput."""
+    import torch
+    p = workloads.h2_softcore()
+    out = sf.run([p], [4096], [1001], h_max=40.0)  # warm-up
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        out = sf.run([p], [4096], [1001], h_max=40.0)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+    ens, _ = sf.sample_initial([p], [4096], [1001])
+    steps = live_steps_of(sf, [p], [4096], ens)
+    best = min(ts)
+    return {"workload": "h2-softcore-800nm-4096", "ms_per_run": best * 1e3,
+            "ms_per_run_median": sorted(ts)[len(ts) // 2] * 1e3, "live_trajectory_steps": steps,
+            "value": steps / best, "unit": "trajectory-steps/s", "precision": "fp64"}
 
 
 def live_steps_of(sf, probs, n_traj, ens):
@@ -521,6 +560,8 @@ def main():
         plan.close()
         del plan
         torch.cuda.empty_cache()
+        variants["small"] = small_variant(sf)
+        print(f"small: {variants['small']}", file=sys.stderr, flush=True)
         variants["analysis"] = analysis_variant(sf, probs, ens, ws, v, offs, lens)
         print(f"analysis: {variants['analysis']}", file=sys.stderr, flush=True)
         variants["saddle"] = saddle_variant(sf, args.n_traj, args.steps, args.warmup)
