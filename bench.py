@@ -136,17 +136,28 @@ def small_variant(sf, reps=5):
             "value": steps / best, "unit": "trajectory-steps/s", "precision": "fp64"}
 
 
-def live_steps_of(sf, probs, n_traj, ens):
+def live_steps_of(sf, probs, n_traj, ens, per_problem=False):
     """Unit of work: sum over live trajectories of N - k0 (RK4 steps)."""
     import torch
-    total, off = 0, 0
+    per, off = [], 0
     for p, n in zip(probs, n_traj):
         N = sf.problem_steps(p)[0]
         k0 = ens.k0[off:off + n].to(torch.int64)
         w = ens.w[off:off + n]
-        total += int(((N - k0) * (w > 0)).sum().item())
+        per.append(int(((N - k0) * (w > 0)).sum().item()))
         off += n
-    return total
+    return per if per_problem else sum(per)
+
+
+def step_roofline(flops, seconds):
+    """Vector-ALU roofline of a whole step (sampling, propagation, dipole,
+    spectra) timed as one: algorithmic flops over the step time against the
+    FP64 vector peak, which also bounds FP32 here (without packed math FP32
+    issues at the FP64 rate)."""
+    achieved = flops / seconds / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+            "time": "whole step"}
 
 
 def spectral_db(sf, prob, v_a, v_b, h_lo, h_hi):
@@ -481,6 +492,8 @@ def main():
           file=sys.stderr, flush=True)
 
     achieved = algo_flops / kern_s / 1e12
+    traffic = measured_traffic("propagate_f64_kernel",
+                               "n2_fixed_0_90_2x1048576") if args.n_traj == 1 << 20 else None
     out = {
         "metric": "HK trajectory-steps/s (FP64)",
         "value": live_steps * args.steps / el,
@@ -500,9 +513,9 @@ def main():
                    "precision": "fp64"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": measured_traffic("propagate_f64_kernel",
-                                                 "n2_fixed_0_90_2x1048576") if args.n_traj == 1 << 20 else None,
+                     "traffic": traffic,
                      "kernel": "propagate_f64_kernel", "kernel_ms": kern_s * 1e3,
+                     "traffic_gb_per_s": (traffic / kern_s / 1e9) if traffic else None,
                      "flops_per_traj_step": flop_step,
                      "flops_per_traj_step_with_recombination": [flops_per_step(p, True) for p in probs]},
     }
@@ -546,14 +559,18 @@ def main():
                              "unit": "trajectory-steps/s", "ms_per_step": sec * 1e3,
                              "tuning": list(tun), "error_vs_fp64": errs,
                              "error_vs_fp64_prefactor_cap_1e3": errs_c,
-                             "speedup_vs_fp64": (el / args.steps) / sec}
+                             "speedup_vs_fp64": (el / args.steps) / sec,
+                             "roofline": step_roofline(algo_flops, sec)}
         # batched cos^4 H2 + N2 over 64 lasers each, persistent plan, graph replay
         wb = workloads.workload_batched(32768)
         tun = autotune.cached(wb["problems"], wb["precision"]) or (1, 8, 1, 1)
         plan, sec = timed_plan(sf, wb["problems"], wb["n_traj"], wb["seeds"], wb["precision"],
                                tun, args.steps, args.warmup, 40.0)
-        ls = live_steps_of(sf, wb["problems"], wb["n_traj"], plan.ens)
+        per = live_steps_of(sf, wb["problems"], wb["n_traj"], plan.ens, per_problem=True)
+        ls = sum(per)
+        bflops = sum(n * flops_per_step(p) for n, p in zip(per, wb["problems"]))
         variants["batched"] = {"workload": wb["name"], "value": ls / sec,
+                               "roofline": step_roofline(bflops, sec),
                                "unit": "trajectory-steps/s", "ms_per_step": sec * 1e3,
                                "live_trajectory_steps": ls, "precision": wb["precision"],
                                "tuning": list(tun), "launch": "one HIP graph per step"}

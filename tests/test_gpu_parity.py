@@ -235,6 +235,18 @@ def test_edge_cases(sf, orc):
     assert s["k0"].max() <= orc.n_steps(p) - 1
 
 
+def test_stretched_molecule_screening(sf, orc):
+    """N2 stretched to R = 20 a.u.: near one centre the other centre's
+    screening exponent lies beyond the cut-off (alpha rho up to ~93), so the
+    kernel evaluates one screening exponential inside and one outside the
+    cut in the same call.  The prefactor cap filters chaotic trajectories."""
+    p = dict(workloads.with_changes(workloads.n2(30.0), **{"target.R": 20.0}), c_max=1e3)
+    (v,), _ = gpu_dipole(sf, [p], [400], [11])
+    vo, _, _ = orc.dipole(p, 11, 0, 400, NTHREADS)
+    assert np.linalg.norm(vo) > 0
+    assert rel_l2(v, vo) < REL_L2
+
+
 # -------------------------------------------------------------- spectrum
 def test_spectrum_matches_oracle(sf, orc):
     import torch
