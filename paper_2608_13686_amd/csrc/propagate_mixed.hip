@@ -3,12 +3,48 @@
 // action S is accumulated in FP64 (from FP32 stage Lagrangians), and the
 // square root of det R with its branch, the recombination element, the
 // amplitude and the dipole sum are FP64.
-// One trajectory per lane, one 64-lane pack per wavefront; the whole state
-// fits in VGPRs (no LDS).
+// One trajectory per lane, one 64-lane pack per wavefront; the monodromy
+// matrix lives in LDS (element-major, lane-minor, 9 KB per wavefront), the
+// rest of the state in VGPRs, so that three wavefronts fit on each SIMD.
 #include "device_common.h"
 
 namespace sfhk {
 namespace {
+
+constexpr int kMonoElems = 36;  // row-major 6x6, rows (q, p), columns (q0, p0)
+
+// M <- M + (P - I) M for the FP32 monodromy in LDS, one column at a time
+// (the next column loaded before the current one is computed); returns the
+// largest |entry| of the new matrix.
+__device__ __forceinline__ float monodromy_step_f32(const StepMatrix<float>& P,
+                                                    float (*mono)[kWave], int lane) {
+  float x[3] = {mono[0][lane], mono[6][lane], mono[12][lane]};
+  float v[3] = {mono[18][lane], mono[24][lane], mono[30][lane]};
+  float mmax = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    __builtin_amdgcn_sched_barrier(0);
+    float xl[3] = {0.0f, 0.0f, 0.0f}, vl[3] = {0.0f, 0.0f, 0.0f};
+    if (c < 5) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        xl[r] = mono[6 * r + c + 1][lane];
+        vl[r] = mono[18 + 6 * r + c + 1][lane];
+      }
+    }
+    float xn[3], vn[3];
+    apply_step_increment(P, x, v, xn, vn);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      mono[6 * r + c][lane] = xn[r];
+      mono[18 + 6 * r + c][lane] = vn[r];
+      mmax = fmaxf(mmax, fmaxf(fabsf(xn[r]), fabsf(vn[r])));
+      x[r] = xl[r];
+      v[r] = vl[r];
+    }
+  }
+  return mmax;
+}
 
 template <int U>
 __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
@@ -16,7 +52,8 @@ __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
                                                const EnsPtrs& e, int32_t* __restrict__ redo,
                                                double* __restrict__ accum,
                                                double* __restrict__ final_state,
-                                               uint64_t capacity, const Pack& pk, int lane) {
+                                               uint64_t capacity, const Pack& pk, int lane,
+                                               float (*mono)[kWave]) {
   const Desc& d = descs[pk.prob];
   const int N = d.N;
   const bool valid = pk.valid;
@@ -35,14 +72,8 @@ __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
   const float hRn[3] = {(float)(d.half_R * n[0]), (float)(d.half_R * n[1]),
                         (float)(d.half_R * n[2])};
   double S = 0.0;
-  float mq[3][6], mp[3][6];
 #pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      mq[r][c] = (c == r) ? 1.0f : 0.0f;
-      mp[r][c] = (c == r + 3) ? 1.0f : 0.0f;
-    }
+  for (int i = 0; i < kMonoElems; ++i) mono[i][lane] = (i % 7 == 0) ? 1.0f : 0.0f;
   double Cre = 1.0, Cim = 0.0, flips = 0.0;
 
   const double hd = d.dt;
@@ -71,8 +102,9 @@ __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
       for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-          Rr[a][b] = 0.5f * (mq[a][b] + mp[a][3 + b]);
-          Ri[a][b] = 0.5f * (ig * mp[a][b] - gm * mq[a][3 + b]);
+          // Mqq[a][b] + Mpp[a][b], (1/g) Mpq[a][b] - g Mqp[a][b]
+          Rr[a][b] = 0.5f * (mono[6 * a + b][lane] + mono[18 + 6 * a + 3 + b][lane]);
+          Ri[a][b] = 0.5f * (ig * mono[18 + 6 * a + b][lane] - gm * mono[6 * a + 3 + b][lane]);
         }
       float Dr, Di;
       det3c(Rr, Ri, Dr, Di);
@@ -151,29 +183,11 @@ __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
     }
     // monodromy: M <- M + (P - I) M with the RK4 step matrix of K1..K4,
     // its identity part left out so that FP32 keeps the O(h^2 K) terms
-    {
-      StepMatrix<float> P;
-      rk4_step_matrix<float, true>(K1, K2, K3, K4, h, P);
-#pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        const float x0[3] = {mq[0][c], mq[1][c], mq[2][c]};
-        const float v0[3] = {mp[0][c], mp[1][c], mp[2][c]};
-        float xn[3], vn[3];
-        apply_step_increment(P, x0, v0, xn, vn);
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-          mq[r][c] = xn[r];
-          mp[r][c] = vn[r];
-        }
-      }
-    }
+    StepMatrix<float> P;
+    rk4_step_matrix<float, true>(K1, K2, K3, K4, h, P);
+    const float mmax = monodromy_step_f32(P, mono, lane);
     // FP32 rounding is amplified by the monodromy matrix: past the bound the
     // trajectory is finished by the FP64 kernel from step k + 1 on
-    float mmax = 0.0f;
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 6; ++c) mmax = fmaxf(mmax, fmaxf(fabsf(mq[r][c]), fabsf(mp[r][c])));
     if (mmax > kMixedFlagNorm) {
       kend = k + 1;
       redo[slot] = kend;
@@ -191,12 +205,7 @@ __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
       f[(SFHK_FS_P + a) * st] = (double)p[a];
     }
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        f[(SFHK_FS_M + 6 * r + c) * st] = (double)mq[r][c];
-        f[(SFHK_FS_M + 6 * (3 + r) + c) * st] = (double)mp[r][c];
-      }
+    for (int i = 0; i < kMonoElems; ++i) f[(SFHK_FS_M + i) * st] = (double)mono[i][lane];
     f[SFHK_FS_S * st] = S;
     f[SFHK_FS_CRE * st] = Cre;
     f[SFHK_FS_CIM * st] = Cim;
@@ -205,24 +214,26 @@ __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
 }
 
 template <int U>
-__global__ void __launch_bounds__(kWave)
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3, 3)))
 propagate_mixed_kernel(const Desc* __restrict__ descs, int n_prob,
                        const double* __restrict__ field, EnsPtrs e, int32_t* __restrict__ redo,
                        double* __restrict__ accum, double* __restrict__ final_state,
                        uint64_t capacity) {
+  __shared__ float mono[kMonoElems][kWave];
   const int lane = threadIdx.x;
   Pack pk;
   if (!find_pack(e, n_prob, blockIdx.x, lane, pk)) return;
-  run_pack_mixed<U>(descs, field, e, redo, accum, final_state, capacity, pk, lane);
+  run_pack_mixed<U>(descs, field, e, redo, accum, final_state, capacity, pk, lane, mono);
 }
 
 template <int U>
-__global__ void __launch_bounds__(kWave)
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3, 3)))
 propagate_mixed_persistent(const Desc* __restrict__ descs, int n_prob,
                            const double* __restrict__ field, EnsPtrs e,
                            int32_t* __restrict__ redo, double* __restrict__ accum,
                            double* __restrict__ final_state, uint64_t capacity,
                            const uint32_t* __restrict__ queue, uint32_t* __restrict__ counter) {
+  __shared__ float mono[kMonoElems][kWave];
   const int lane = threadIdx.x;
   const uint32_t total = e.pack_start[n_prob];
   for (;;) {
@@ -232,7 +243,7 @@ propagate_mixed_persistent(const Desc* __restrict__ descs, int n_prob,
     if (idx >= total) break;
     Pack pk;
     find_pack(e, n_prob, queue[idx], lane, pk);
-    run_pack_mixed<U>(descs, field, e, redo, accum, final_state, capacity, pk, lane);
+    run_pack_mixed<U>(descs, field, e, redo, accum, final_state, capacity, pk, lane, mono);
   }
 }
 
