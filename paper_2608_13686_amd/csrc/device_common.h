@@ -218,7 +218,7 @@ __device__ __forceinline__ void potential(const Desc& d, const T hRn[3], const T
     dx[c] = c == 0 ? q[0] - hRn[0] : q[0] + hRn[0];
     dy[c] = c == 0 ? q[1] - hRn[1] : q[1] + hRn[1];
     dz[c] = c == 0 ? q[2] - hRn[2] : q[2] + hRn[2];
-    r2[c] = dx[c] * dx[c] + dy[c] * dy[c] + dz[c] * dz[c] + PC::eps2(d, c);
+    r2[c] = fma(dz[c], dz[c], fma(dy[c], dy[c], fma(dx[c], dx[c], PC::eps2(d, c))));
     s[c] = rsqrt_t(r2[c]);
   }
   if (d.screened) {
@@ -349,8 +349,8 @@ __device__ __forceinline__ void apply_step_matrix(const StepMatrix<T>& P, const 
 }
 
 // M <- P M for the monodromy held in LDS (element-major, lane-minor: row-major
-// 6x6, rows (q, p), columns (q0, p0)), one column at a time, and R =
-// 1/2 (Mqq + Mpp - i g Mqp + (i/g) Mpq) rebuilt from the new columns
+// 6x6, rows (q, p), columns (q0, p0)), one column at a time, and
+// R2 = 2R = Mqq + Mpp - i g Mqp + (i/g) Mpq rebuilt from the new columns
 // (column c < 3 holds Mqq[:, c] and Mpq[:, c], column c + 3 holds Mqp[:, c]
 // and Mpp[:, c]).  The next column is loaded before the current one is
 // computed, so that the LDS latency is hidden behind its arithmetic; the
@@ -379,11 +379,11 @@ __device__ __forceinline__ void monodromy_step(const StepMatrix<double>& P, doub
       mono[6 * r + c][lane] = xn[r];
       mono[18 + 6 * r + c][lane] = vn[r];
       if (c < 3) {
-        Rr[r][c] = 0.5 * xn[r];
-        Ri[r][c] = 0.5 * inv_gamma * vn[r];
+        Rr[r][c] = xn[r];
+        Ri[r][c] = inv_gamma * vn[r];
       } else {
-        Rr[r][c - 3] += 0.5 * vn[r];
-        Ri[r][c - 3] -= 0.5 * gamma * xn[r];
+        Rr[r][c - 3] += vn[r];
+        Ri[r][c - 3] -= gamma * xn[r];
       }
       x[r] = xl[r];
       v[r] = vl[r];
@@ -419,19 +419,24 @@ __device__ __forceinline__ bool find_pack(const EnsPtrs& e, int n_prob, uint32_t
   return true;
 }
 
-// det R of the complex 3x3 R = Rr + i Ri (cofactor expansion along row 0).
+// det R of the complex 3x3 R = Rr + i Ri (cofactor expansion along row 0),
+// each term one multiply-add chain.
 template <typename T>
 __device__ __forceinline__ void det3c(const T Rr[3][3], const T Ri[3][3], T& Dr, T& Di) {
-  const T c0r = Rr[1][1] * Rr[2][2] - Ri[1][1] * Ri[2][2] - (Rr[1][2] * Rr[2][1] - Ri[1][2] * Ri[2][1]);
-  const T c0i = Rr[1][1] * Ri[2][2] + Ri[1][1] * Rr[2][2] - (Rr[1][2] * Ri[2][1] + Ri[1][2] * Rr[2][1]);
-  const T c1r = Rr[1][0] * Rr[2][2] - Ri[1][0] * Ri[2][2] - (Rr[1][2] * Rr[2][0] - Ri[1][2] * Ri[2][0]);
-  const T c1i = Rr[1][0] * Ri[2][2] + Ri[1][0] * Rr[2][2] - (Rr[1][2] * Ri[2][0] + Ri[1][2] * Rr[2][0]);
-  const T c2r = Rr[1][0] * Rr[2][1] - Ri[1][0] * Ri[2][1] - (Rr[1][1] * Rr[2][0] - Ri[1][1] * Ri[2][0]);
-  const T c2i = Rr[1][0] * Ri[2][1] + Ri[1][0] * Rr[2][1] - (Rr[1][1] * Ri[2][0] + Ri[1][1] * Rr[2][0]);
-  Dr = (Rr[0][0] * c0r - Ri[0][0] * c0i) - (Rr[0][1] * c1r - Ri[0][1] * c1i) +
-       (Rr[0][2] * c2r - Ri[0][2] * c2i);
-  Di = (Rr[0][0] * c0i + Ri[0][0] * c0r) - (Rr[0][1] * c1i + Ri[0][1] * c1r) +
-       (Rr[0][2] * c2i + Ri[0][2] * c2r);
+  // complex 2x2 minors of rows 1, 2: m_j = R[1][a] R[2][b] - R[1][b] R[2][a]
+  T mr[3], mi[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int a = j == 0 ? 1 : 0, b = j == 2 ? 1 : 2;
+    mr[j] = fma(Rr[1][a], Rr[2][b],
+                fma(-Ri[1][a], Ri[2][b], fma(-Rr[1][b], Rr[2][a], Ri[1][b] * Ri[2][a])));
+    mi[j] = fma(Rr[1][a], Ri[2][b],
+                fma(Ri[1][a], Rr[2][b], fma(-Rr[1][b], Ri[2][a], -(Ri[1][b] * Rr[2][a]))));
+  }
+  Dr = fma(Rr[0][0], mr[0], fma(-Ri[0][0], mi[0], fma(-Rr[0][1], mr[1],
+       fma(Ri[0][1], mi[1], fma(Rr[0][2], mr[2], -(Ri[0][2] * mi[2]))))));
+  Di = fma(Rr[0][0], mi[0], fma(Ri[0][0], mr[0], fma(-Rr[0][1], mi[1],
+       fma(-Ri[0][1], mr[1], fma(Rr[0][2], mi[2], Ri[0][2] * mr[2])))));
 }
 
 // HK prefactor C = sqrt(D), D = det R: the principal root continued along
@@ -447,15 +452,12 @@ __device__ __forceinline__ void sqrt_continued(double Dr, double Di, double& Cre
   const double mag = m2 * rsqrt_nr(m2);
   const double u = 0.5 * (mag + fabs(Dr));
   const double ru = rsqrt_nr(u);
+  // a square root (either sign: the continuation below picks it): (big,
+  // small) for Dr >= 0, (small, big) for Dr < 0, each free of cancellation
   const double big = u * ru, small = 0.5 * Di * ru;
-  double sr, si;
-  if (Dr >= 0.0) {
-    sr = big;
-    si = small;
-  } else {
-    sr = fabs(small);
-    si = Di < 0.0 ? -big : big;
-  }
+  const bool pos = Dr >= 0.0;
+  double sr = pos ? big : small;
+  double si = pos ? small : big;
   double xr = sr * Cre + si * Cim;
   const double xi = si * Cre - sr * Cim;
   if (xr < 0.0) {
@@ -468,11 +470,13 @@ __device__ __forceinline__ void sqrt_continued(double Dr, double Di, double& Cre
   Cim = si;
 }
 
-__device__ __forceinline__ void prefactor_step(const double Rr[3][3], const double Ri[3][3],
+// One prefactor step from R2 = 2R (kept doubled: the factors 1/2 are left out
+// of its entries, and det R = det R2 / 8 exactly, a power-of-two scaling).
+__device__ __forceinline__ void prefactor_step(const double R2r[3][3], const double R2i[3][3],
                                                double& Cre, double& Cim, double& flips) {
   double Dr, Di;
-  det3c(Rr, Ri, Dr, Di);
-  sqrt_continued(Dr, Di, Cre, Cim, flips);
+  det3c(R2r, R2i, Dr, Di);
+  sqrt_continued(0.125 * Dr, 0.125 * Di, Cre, Cim, flips);
 }
 
 // Re a_k of the amplitude a = -w C e^{i Phi} <psi0|k_z|p,q>,

@@ -44,13 +44,14 @@ __device__ __forceinline__ void run_pack(const Desc* __restrict__ descs,
   double S = 0.0;
 #pragma unroll
   for (int i = 0; i < kMonoElems; ++i) mono[i][lane] = (i % 7 == 0) ? 1.0 : 0.0;
-  // HK matrix R = 1/2 (Mqq + Mpp - i g Mqp + (i/g) Mpq) of the current M
+  // twice the HK matrix, R2 = 2R = Mqq + Mpp - i g Mqp + (i/g) Mpq, of the
+  // current M
   double Rr[3][3], Ri[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      Rr[a][b] = a == b ? 1.0 : 0.0;
+      Rr[a][b] = a == b ? 2.0 : 0.0;
       Ri[a][b] = 0.0;
     }
   double Cre = 1.0, Cim = 0.0;

@@ -102,13 +102,14 @@ __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
       for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-          // Mqq[a][b] + Mpp[a][b], (1/g) Mpq[a][b] - g Mqp[a][b]
-          Rr[a][b] = 0.5f * (mono[6 * a + b][lane] + mono[18 + 6 * a + 3 + b][lane]);
-          Ri[a][b] = 0.5f * (ig * mono[18 + 6 * a + b][lane] - gm * mono[6 * a + 3 + b][lane]);
+          // R2 = 2R: Mqq[a][b] + Mpp[a][b], (1/g) Mpq[a][b] - g Mqp[a][b]
+          Rr[a][b] = mono[6 * a + b][lane] + mono[18 + 6 * a + 3 + b][lane];
+          Ri[a][b] = ig * mono[18 + 6 * a + b][lane] - gm * mono[6 * a + 3 + b][lane];
         }
       float Dr, Di;
       det3c(Rr, Ri, Dr, Di);
-      sqrt_continued((double)Dr, (double)Di, Cre, Cim, flips);
+      // det R = det R2 / 8 (exact)
+      sqrt_continued(0.125 * (double)Dr, 0.125 * (double)Di, Cre, Cim, flips);
       if (d.c_max2 > 0.0 && Cre * Cre + Cim * Cim > d.c_max2) {
         kend = k;  // prefactor cap: no contribution from here on
         kcap = k;

@@ -76,14 +76,14 @@ serve_slice_f64(const ReqDev* __restrict__ reqs, SliceTable tab) {
   }
   const double p0q0 =
       R.px[slot] * R.qx[slot] + R.py[slot] * R.qy[slot] + R.pz[slot] * R.qz[slot] + R.dph[slot];
+  // R2 = 2R = Mqq + Mpp - i g Mqp + (i/g) Mpq of the restored M
   double Rr[3][3], Ri[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      Rr[a][b] = 0.5 * (mono[6 * a + b][lane] + mono[18 + 6 * a + 3 + b][lane]);
-      Ri[a][b] = 0.5 * d.inv_gamma * mono[18 + 6 * a + b][lane] -
-                 0.5 * d.gamma * mono[6 * a + 3 + b][lane];
+      Rr[a][b] = mono[6 * a + b][lane] + mono[18 + 6 * a + 3 + b][lane];
+      Ri[a][b] = d.inv_gamma * mono[18 + 6 * a + b][lane] - d.gamma * mono[6 * a + 3 + b][lane];
     }
 
   const double h = d.dt;
