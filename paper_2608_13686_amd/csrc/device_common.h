@@ -391,9 +391,23 @@ __device__ __forceinline__ void monodromy_step(const StepMatrix<double>& P, doub
   }
 }
 
+// x from lane (lane ^ m) within each 32-lane half (ds_swizzle, bit-mask
+// mode: and 0x1f, or 0, xor m); the pattern is an immediate, no address VGPR
+template <int M>
+__device__ __forceinline__ double swizzle_xor(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_swizzle((int)(uint32_t)b, (M << 10) | 0x1f);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_swizzle((int)(uint32_t)(b >> 32), (M << 10) | 0x1f);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  v += __shfl_xor(v, 32, kWave);
+  v += swizzle_xor<16>(v);
+  v += swizzle_xor<8>(v);
+  v += swizzle_xor<4>(v);
+  v += swizzle_xor<2>(v);
+  v += swizzle_xor<1>(v);
   return v;
 }
 
@@ -547,7 +561,8 @@ __device__ __forceinline__ double amplitude_re(const Desc& d, const double n[3],
   return -w * (er_ * rr - ei_ * ri);
 }
 
-// Dipole deposit: the wavefront sum of Re a_k is kept by lane (k mod 64);
+// Dipole deposit: the wavefront sum of Re a_k (one cross-half exchange, then
+// five swizzle levels) is kept by lane (k mod 64);
 // every 64 steps (and at the last step) the wavefront adds its 64 sums to the
 // accumulator with one coalesced atomic.  Uniform control flow required.
 __device__ __forceinline__ void deposit(double re_a, int k, int N, int lane, double& acc_reg,
