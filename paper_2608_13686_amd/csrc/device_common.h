@@ -208,19 +208,39 @@ template <> struct PotConst<float> {
 // so that grad V_i = s^2 t d and
 //   Hess V_i = s^2 t I + c2 d d^T,  c2 = (V_i'' - V_i'/rho) s^2
 //                                      = -s^3 (3 s t + alpha A u).
+// Position relative to both nuclei: d_c = q - R_c (centre 0 at +R/2 n,
+// hRn = R/2 n) and the softened squared distances r2_c = |d_c|^2 + eps2_c.
+// Computed once per step at q_k for the recombination amplitude and the
+// first RK4 stage.
 template <typename T>
-__device__ __forceinline__ void potential(const Desc& d, const T hRn[3], const T q[3], T& V,
-                                          T g[3], T K[6]) {
-  using PC = PotConst<T>;
-  T dx[2], dy[2], dz[2], r2[2], s[2], u[2] = {T(0), T(0)};
+struct Geom {
+  T dx[2], dy[2], dz[2], r2[2];
+};
+
+template <typename T>
+__device__ __forceinline__ void geometry(const Desc& d, const T hRn[3], const T q[3],
+                                         Geom<T>& G) {
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    dx[c] = c == 0 ? q[0] - hRn[0] : q[0] + hRn[0];
-    dy[c] = c == 0 ? q[1] - hRn[1] : q[1] + hRn[1];
-    dz[c] = c == 0 ? q[2] - hRn[2] : q[2] + hRn[2];
-    r2[c] = fma(dz[c], dz[c], fma(dy[c], dy[c], fma(dx[c], dx[c], PC::eps2(d, c))));
-    s[c] = rsqrt_t(r2[c]);
+    G.dx[c] = c == 0 ? q[0] - hRn[0] : q[0] + hRn[0];
+    G.dy[c] = c == 0 ? q[1] - hRn[1] : q[1] + hRn[1];
+    G.dz[c] = c == 0 ? q[2] - hRn[2] : q[2] + hRn[2];
+    G.r2[c] = fma(G.dz[c], G.dz[c],
+                  fma(G.dy[c], G.dy[c], fma(G.dx[c], G.dx[c], PotConst<T>::eps2(d, c))));
   }
+}
+
+template <typename T>
+__device__ __forceinline__ void potential(const Desc& d, const Geom<T>& G, T& V, T g[3],
+                                          T K[6]) {
+  using PC = PotConst<T>;
+  const T* dx = G.dx;
+  const T* dy = G.dy;
+  const T* dz = G.dz;
+  const T* r2 = G.r2;
+  T s[2], u[2] = {T(0), T(0)};
+#pragma unroll
+  for (int c = 0; c < 2; ++c) s[c] = rsqrt_t(r2[c]);
   if (d.screened) {
     // both centres' screening factors at once (an electron far from one
     // centre is far from the other); the argument is capped where e^{-y}
@@ -257,6 +277,14 @@ __device__ __forceinline__ void potential(const Desc& d, const T hRn[3], const T
   K[0] += diag;
   K[1] += diag;
   K[2] += diag;
+}
+
+template <typename T>
+__device__ __forceinline__ void potential(const Desc& d, const T hRn[3], const T q[3], T& V,
+                                          T g[3], T K[6]) {
+  Geom<T> G;
+  geometry(d, hRn, q, G);
+  potential(d, G, V, g, K);
 }
 
 // y = K x for the symmetric 3x3 K
@@ -500,17 +528,12 @@ __device__ __forceinline__ void prefactor_step(const double R2r[3][3], const dou
 // factor).  Shells below the far-field cut are skipped (their terms are
 // < 1e-30).
 __device__ __forceinline__ double amplitude_re(const Desc& d, const double n[3],
-                                               const double p[3], const double q[3],
+                                               const double p[3], const Geom<double>& G,
                                                double Cre, double Cim, double S, double tk,
                                                double t0, double p0q0, double w) {
   const double pp = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
-  double dd[2];
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const double s = c == 0 ? d.half_R : -d.half_R;
-    const double x = s * n[0] - q[0], y = s * n[1] - q[1], z = s * n[2] - q[2];
-    dd[c] = x * x + y * y + z * z;
-  }
+  // |R_a - q|^2 from the softened distances of the geometry at q
+  const double dd[2] = {G.r2[0] - d.eps2[0], G.r2[1] - d.eps2[1]};
   // ln(1 + |C|) bound from the binary exponent of 1 + |C|^2
   const double cc = 1.0 + Cre * Cre + Cim * Cim;
   const double lnC = 0.3466 * (double)(((int)(__double_as_longlong(cc) >> 52) & 0x7ff) - 1022);
@@ -525,10 +548,10 @@ __device__ __forceinline__ double amplitude_re(const Desc& d, const double n[3],
   double rr = 0.0, ri = 0.0;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    const double s = c == 0 ? d.half_R : -d.half_R;
-    const double x = s * n[0] - q[0], y = s * n[1] - q[1], dz = s * n[2] - q[2];
-    const double pd = p[0] * x + p[1] * y + p[2] * dz;  // p.(R_a - q)
-    const double nd = n[0] * x + n[1] * y + n[2] * dz;  // n.(R_a - q)
+    // R_a - q = -d_c
+    const double dz = -G.dz[c];
+    const double pd = -(p[0] * G.dx[c] + p[1] * G.dy[c] + p[2] * G.dz[c]);  // p.(R_a - q)
+    const double nd = -(n[0] * G.dx[c] + n[1] * G.dy[c] + n[2] * G.dz[c]);  // n.(R_a - q)
     const double ddc = dd[c];
     const int j0 = c == 0 ? 0 : d.n_shell0, j1 = c == 0 ? d.n_shell0 : d.n_shell;
     for (int j = j0; j < j1; ++j) {

@@ -117,7 +117,10 @@ __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
       } else {
         const double pd_[3] = {(double)p[0], (double)p[1], (double)p[2]};
         const double qd_[3] = {(double)q[0], (double)q[1], (double)q[2]};
-        re_a = amplitude_re(d, n, pd_, qd_, Cre, Cim, S, d.t_first + (double)k * hd, t0, p0q0,
+        const double hRnd[3] = {d.half_R * n[0], d.half_R * n[1], d.half_R * n[2]};
+        Geom<double> Gd;
+        geometry(d, hRnd, qd_, Gd);
+        re_a = amplitude_re(d, n, pd_, Gd, Cre, Cim, S, d.t_first + (double)k * hd, t0, p0q0,
                             w);
       }
     }

@@ -95,24 +95,26 @@ serve_slice_f64(const ReqDev* __restrict__ reqs, SliceTable tab) {
   for (; k < k_to; ++k) {
     bool live = k >= k0 && k < kend;
     double re_a = 0.0;
+    const double hRn[3] = {d.half_R * n[0], d.half_R * n[1], d.half_R * n[2]};
+    Geom<double> Gk;  // geometry at q_k: amplitude and first RK4 stage
+    geometry(d, hRn, q, Gk);
     if (live) {
       prefactor_step(Rr, Ri, Cre, Cim, flips);
       if (d.c_max2 > 0.0 && Cre * Cre + Cim * Cim > d.c_max2) {
         kend = k;
         live = false;
       } else {
-        re_a = amplitude_re(d, n, p, q, Cre, Cim, S, d.t_first + (double)k * h, t0, p0q0, w8);
+        re_a = amplitude_re(d, n, p, Gk, Cre, Cim, S, d.t_first + (double)k * h, t0, p0q0, w8);
       }
     }
     deposit(re_a, k, N, lane, acc_reg, acc);
     if (k >= N || !live) continue;
 
     const double Ek = fe[2 * k], Eh = fe[2 * k + 1], E1 = fe[2 * k + 2];
-    const double hRn[3] = {d.half_R * n[0], d.half_R * n[1], d.half_R * n[2]};
     double K1[6], K2[6], K3[6], K4[6];
     double V, g[3];
     double sq[3], sp3[3], sS, yq[3], yp[3];
-    potential(d, hRn, q, V, g, K1);
+    potential(d, Gk, V, g, K1);
     {
       const double kp[3] = {-g[0], -g[1], -g[2] - Ek};
       const double kS = 0.5 * (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]) - V - q[2] * Ek;
