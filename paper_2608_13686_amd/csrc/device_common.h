@@ -260,7 +260,8 @@ __device__ __forceinline__ void potential(const Desc& d, const Geom<T>& G, T& V,
     const T t = Z * s[c] + PC::adZ(d, c) * u[c];
     const T s2 = s[c] * s[c];
     const T c1 = s2 * t;  // V_i'/rho
-    const T c2 = -(s2 * s[c]) * (T(3) * s[c] * t + PC::a2dZ(d, c) * u[c]);
+    // c2 = -s^3 (3 s t + alpha^2 dZ u) = -s^2 (3 c1 + alpha^2 dZ u s)
+    const T c2 = -s2 * fma(T(3), c1, PC::a2dZ(d, c) * u[c] * s[c]);
     V -= Z * s[c];
     g[0] += c1 * dx[c];
     g[1] += c1 * dy[c];
