@@ -173,13 +173,14 @@ __device__ __forceinline__ void exp_neg2_t(float y0, float y1, float& e0, float&
 // the terms of dZ e^{-alpha rho} in V, V' and V'' are below 1e-21 of the
 // Z_inf terms, far under one rounding unit, so they are not evaluated; when
 // they are, the exponent is capped at kScreenCap (e^{-700} is nothing next to
-// Z_inf, and the cap keeps the exponential in its range).  Recombination: a GTO
-// primitive whose Gaussian exponent satisfies er + ln(1 + |C|) < kRecombFar
-// contributes less than 1e-30 to a dipole sample (|b|-dependent factors and
-// norms are bounded by 1e4), so its exp and sincos are not evaluated.
+// Z_inf, and the cap keeps the exponential in its range).  Recombination: a
+// shell whose Gaussian exponent satisfies er + ln(1 + |C|) < kRecombFar
+// contributes less than e^-45 1e4 = 3e-16 to a dipole sample (|b|-dependent
+// factors and norms are bounded by 1e4): below one rounding unit of an O(1)
+// amplitude, so its exp and sincos are not evaluated.
 constexpr double kScreenFar = 60.0;
 constexpr double kScreenCap = 700.0;
-constexpr double kRecombFar = -75.0;
+constexpr double kRecombFar = -45.0;
 
 template <typename T> struct PotConst;
 template <> struct PotConst<double> {
@@ -527,7 +528,7 @@ __device__ __forceinline__ void prefactor_step(const double R2r[3][3], const dou
 // element as a sum of Gaussian moments of the GTO primitives, taken shell by
 // shell (the primitives of one centre and exponent share the Gaussian
 // factor).  Shells below the far-field cut are skipped (their terms are
-// < 1e-30).
+// < 3e-16).
 __device__ __forceinline__ double amplitude_re(const Desc& d, const double n[3],
                                                const double p[3], const Geom<double>& G,
                                                double Cre, double Cim, double S, double tk,
