@@ -170,15 +170,17 @@ __device__ __forceinline__ void exp_neg2_t(float y0, float y1, float& e0, float&
 }
 
 // Far-field cut-offs.  Screening: for alpha*rho > kScreenFar at both centres
-// the terms of dZ e^{-alpha rho} in V, V' and V'' are below 1e-21 of the
-// Z_inf terms, far under one rounding unit, so they are not evaluated; when
+// the terms of dZ e^{-alpha rho} in V, V' and V'' are at most
+// (alpha rho)^2 e^{-alpha rho} dZ / (2 Z_inf) < 2.9e-17 dZ/Z_inf of the Z_inf
+// terms (4e-16 for N2's Table I values), at the rounding level, so they are
+// not evaluated; when
 // they are, the exponent is capped at kScreenCap (e^{-700} is nothing next to
 // Z_inf, and the cap keeps the exponential in its range).  Recombination: a
 // shell whose Gaussian exponent satisfies er + ln(1 + |C|) < kRecombFar
 // contributes less than e^-45 1e4 = 3e-16 to a dipole sample (|b|-dependent
 // factors and norms are bounded by 1e4): below one rounding unit of an O(1)
 // amplitude, so its exp and sincos are not evaluated.
-constexpr double kScreenFar = 60.0;
+constexpr double kScreenFar = 45.0;
 constexpr double kScreenCap = 700.0;
 constexpr double kRecombFar = -45.0;
 
