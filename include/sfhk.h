@@ -265,7 +265,7 @@ typedef struct {
   int32_t persistent;    /* 0: one wavefront per 64-lane pack, packs in (problem, birth) order;
                             1: a persistent grid pulls packs, longest first, from a device queue */
   int32_t waves_per_cu;  /* persistent grid = 256 CUs x waves_per_cu wavefronts, 1..32 (0: 8) */
-  int32_t step_unroll;   /* RK4 steps per loop trip: 1 or 2 (0: 1) */
+  int32_t step_unroll;   /* RK4 steps per loop trip: 1, 2 or 4 (0: 1) */
   int32_t traj_per_lane; /* trajectories per lane: 1 (0: 1); the FP64 state of one trajectory
                             already fills the register budget of two wavefronts per SIMD */
 } sfhk_tuning;

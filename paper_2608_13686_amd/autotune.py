@@ -20,8 +20,8 @@ from . import Plan
 
 CACHE_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning")
 
-CANDIDATES = [(0, 8, 1, 1), (0, 8, 2, 1)] + [(1, w, u, 1) for w in (4, 8, 12, 16)
-                                                 for u in (1, 2)]
+CANDIDATES = [(0, 8, u, 1) for u in (1, 2, 4)] + [(1, w, u, 1) for w in (4, 8, 12, 16)
+                                                    for u in (1, 2, 4)]
 
 
 def cache_key(probs, precision):

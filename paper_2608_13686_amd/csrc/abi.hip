@@ -690,7 +690,7 @@ sfhk_status sfhk_plan_create(const sfhk_problem* probs, int32_t n_prob,
     if (t.traj_per_lane == 0) t.traj_per_lane = 1;
   }
   if ((t.persistent != 0 && t.persistent != 1) || t.waves_per_cu < 1 || t.waves_per_cu > 32 ||
-      (t.step_unroll != 1 && t.step_unroll != 2))
+      (t.step_unroll != 1 && t.step_unroll != 2 && t.step_unroll != 4))
     return fail(SFHK_E_INVALID, "tuning out of range");
   if (t.traj_per_lane != 1)
     return fail(SFHK_E_UNSUPPORTED, "traj_per_lane %d: only 1 fits the register budget",

@@ -258,21 +258,22 @@ hipError_t launch_propagate_mixed(const Desc* descs, int n_prob, const double* f
                                   double* final_state, uint64_t capacity, hipStream_t s,
                                   const LaunchCfg& cfg) {
   if (max_packs == 0) return hipSuccess;
+  auto persistent = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3(cfg.grid), dim3(kWave), 0, s, descs, n_prob, field, e, redo,
+                       accum, final_state, capacity, cfg.queue, cfg.counter);
+  };
+  auto per_pack = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3(max_packs), dim3(kWave), 0, s, descs, n_prob, field, e, redo,
+                       accum, final_state, capacity);
+  };
   if (cfg.persistent) {
-    if (cfg.unroll == 2)
-      hipLaunchKernelGGL(propagate_mixed_persistent<2>, dim3(cfg.grid), dim3(kWave), 0, s, descs,
-                         n_prob, field, e, redo, accum, final_state, capacity, cfg.queue,
-                         cfg.counter);
-    else
-      hipLaunchKernelGGL(propagate_mixed_persistent<1>, dim3(cfg.grid), dim3(kWave), 0, s, descs,
-                         n_prob, field, e, redo, accum, final_state, capacity, cfg.queue,
-                         cfg.counter);
-  } else if (cfg.unroll == 2) {
-    hipLaunchKernelGGL(propagate_mixed_kernel<2>, dim3(max_packs), dim3(kWave), 0, s, descs,
-                       n_prob, field, e, redo, accum, final_state, capacity);
+    if (cfg.unroll == 4) persistent(propagate_mixed_persistent<4>);
+    else if (cfg.unroll == 2) persistent(propagate_mixed_persistent<2>);
+    else persistent(propagate_mixed_persistent<1>);
   } else {
-    hipLaunchKernelGGL(propagate_mixed_kernel<1>, dim3(max_packs), dim3(kWave), 0, s, descs,
-                       n_prob, field, e, redo, accum, final_state, capacity);
+    if (cfg.unroll == 4) per_pack(propagate_mixed_kernel<4>);
+    else if (cfg.unroll == 2) per_pack(propagate_mixed_kernel<2>);
+    else per_pack(propagate_mixed_kernel<1>);
   }
   return hipGetLastError();
 }

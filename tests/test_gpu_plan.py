@@ -46,7 +46,8 @@ def stepwise(sf, probs, n, seeds, h_max):
     return [v.cpu().numpy() for v in out["v"]], [y.cpu().numpy() for y in out["yield"]]
 
 
-@pytest.mark.parametrize("tuning", [(0, 8, 1, 1), (1, 8, 1, 1), (1, 4, 2, 1)])
+@pytest.mark.parametrize("tuning", [(0, 8, 1, 1), (1, 8, 1, 1), (1, 4, 2, 1), (0, 8, 4, 1),
+                                    (1, 12, 4, 1)])
 def test_plan_equals_stepwise_path(sf, tuning):
     import torch
     probs, n, seeds = batch()
