@@ -134,6 +134,55 @@ __device__ __forceinline__ void exp_neg2_t(double y0, double y1, double& e0, dou
   exp_neg2(y0, y1, e0, e1);
 }
 
+// The same constants held in VGPRs for a whole kernel, for kernels with
+// registers to spare: made opaque once (so that the compiler neither folds
+// them back into literals nor rematerialises them), then read by VOP3 FMAs
+// with no scalar moves at the point of use.
+struct ExpK {
+  double c[13];
+};
+__device__ __forceinline__ ExpK make_expk() {
+  ExpK k;
+  const double v[13] = {-1.4426950408889634, 0.6931471805599453, 2.3190468138462996e-17,
+                        2.5100375832561234e-08, 2.7620075879983367e-07, 2.7557268480310024e-06,
+                        2.4801521322368692e-05, 0.00019841269863040545, 0.0013888888917196719,
+                        0.008333333333330065, 0.041666666666624164, 0.16666666666666669,
+                        0.5000000000000001};
+#pragma unroll
+  for (int i = 0; i < 13; ++i) {
+    k.c[i] = v[i];
+    asm volatile("" : "+v"(k.c[i]));
+  }
+  return k;
+}
+__device__ __forceinline__ double fma_vvv(double a, double b, double c) {  // a b + c
+  double d;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+// exp_neg2 with the constants of k, in the same operation order
+__device__ __forceinline__ void exp_neg2_v(double y0, double y1, double& e0, double& e1,
+                                           const ExpK& k) {
+  const double n0 = __builtin_rint(y0 * k.c[0]), n1 = __builtin_rint(y1 * k.c[0]);
+  double r0, r1;
+  asm("v_fma_f64 %0, -%1, %2, -%3" : "=v"(r0) : "v"(n0), "v"(k.c[1]), "v"(y0));
+  asm("v_fma_f64 %0, -%1, %2, -%3" : "=v"(r1) : "v"(n1), "v"(k.c[1]), "v"(y1));
+  asm("v_fma_f64 %0, -%1, %2, %3" : "=v"(r0) : "v"(n0), "v"(k.c[2]), "v"(r0));
+  asm("v_fma_f64 %0, -%1, %2, %3" : "=v"(r1) : "v"(n1), "v"(k.c[2]), "v"(r1));
+  double q0 = fma_vvv(r0, k.c[3], k.c[4]), q1 = fma_vvv(r1, k.c[3], k.c[4]);
+#pragma unroll
+  for (int i = 5; i < 13; ++i) {
+    q0 = fma_vvv(q0, r0, k.c[i]);
+    q1 = fma_vvv(q1, r1, k.c[i]);
+  }
+  q0 = fma(q0, r0, 1.0);
+  q1 = fma(q1, r1, 1.0);
+  q0 = fma(q0, r0, 1.0);
+  q1 = fma(q1, r1, 1.0);
+  e0 = __builtin_amdgcn_ldexp(q0, (int)n0);
+  e1 = __builtin_amdgcn_ldexp(q1, (int)n1);
+}
+
 // sin x and cos x for |x| < 2^31.  x = n pi/2 + r with n = rint(2x/pi) and
 // |r| <= pi/4 (pi/2 in two parts; the first FMA is exact); on |r| <= pi/4,
 // sin r = r + r z S(z) and cos r = 1 - z/2 + z^2 C(z), z = r^2, with S and C
@@ -233,9 +282,11 @@ __device__ __forceinline__ void geometry(const Desc& d, const T hRn[3], const T 
   }
 }
 
+// ek: the exponential's constants in VGPRs (FP64 only; null: built in
+// SGPRs at their use).
 template <typename T>
 __device__ __forceinline__ void potential(const Desc& d, const Geom<T>& G, T& V, T g[3],
-                                          T K[6]) {
+                                          T K[6], const ExpK* ek = nullptr) {
   using PC = PotConst<T>;
   const T* dx = G.dx;
   const T* dy = G.dy;
@@ -249,8 +300,17 @@ __device__ __forceinline__ void potential(const Desc& d, const Geom<T>& G, T& V,
     // centre is far from the other); the argument is capped where e^{-y}
     // is far below a rounding unit of Z_inf
     const T ar0 = PC::alpha(d, 0) * (r2[0] * s[0]), ar1 = PC::alpha(d, 1) * (r2[1] * s[1]);
-    if (ar0 < T(kScreenFar) || ar1 < T(kScreenFar))
-      exp_neg2_t(fmin(ar0, T(kScreenCap)), fmin(ar1, T(kScreenCap)), u[0], u[1]);
+    if (ar0 < T(kScreenFar) || ar1 < T(kScreenFar)) {
+      if constexpr (sizeof(T) == sizeof(double)) {
+        if (ek) {
+          exp_neg2_v(fmin(ar0, T(kScreenCap)), fmin(ar1, T(kScreenCap)), u[0], u[1], *ek);
+        } else {
+          exp_neg2(fmin(ar0, T(kScreenCap)), fmin(ar1, T(kScreenCap)), u[0], u[1]);
+        }
+      } else {
+        exp_neg2_t(fmin(ar0, T(kScreenCap)), fmin(ar1, T(kScreenCap)), u[0], u[1]);
+      }
+    }
   }
   V = T(0);
   g[0] = g[1] = g[2] = T(0);
@@ -285,10 +345,10 @@ __device__ __forceinline__ void potential(const Desc& d, const Geom<T>& G, T& V,
 
 template <typename T>
 __device__ __forceinline__ void potential(const Desc& d, const T hRn[3], const T q[3], T& V,
-                                          T g[3], T K[6]) {
+                                          T g[3], T K[6], const ExpK* ek = nullptr) {
   Geom<T> G;
   geometry(d, hRn, q, G);
-  potential(d, G, V, g, K);
+  potential(d, G, V, g, K, ek);
 }
 
 // y = K x for the symmetric 3x3 K

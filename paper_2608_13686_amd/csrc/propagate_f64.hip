@@ -17,8 +17,10 @@ namespace {
 constexpr int kMonoElems = 36;  // row-major 6x6, rows (q, p), columns (q0, p0)
 
 // One 64-lane pack: every live lane runs its trajectory from its birth step
-// to t_N.  U consecutive steps are unrolled per loop trip.
-template <int U>
+// to t_N.  U consecutive steps are unrolled per loop trip.  VK: the screening
+// exponential's constants are kept in VGPRs (the per-pack kernel has the
+// registers; the persistent one would spill).
+template <int U, bool VK>
 __device__ __forceinline__ void run_pack(const Desc* __restrict__ descs,
                                          const double* __restrict__ field, const EnsPtrs& e,
                                          const int32_t* __restrict__ dep_from,
@@ -64,6 +66,9 @@ __device__ __forceinline__ void run_pack(const Desc* __restrict__ descs,
   double acc_reg = 0.0;
 
   int kend = N + 1;  // first step without contribution (prefactor cap)
+  ExpK ekv;
+  if constexpr (VK) ekv = make_expk();
+  const ExpK* ek = VK ? &ekv : nullptr;
 
   for (int kc = kmin; kc <= N; kc += U) {
 #pragma unroll
@@ -94,7 +99,7 @@ __device__ __forceinline__ void run_pack(const Desc* __restrict__ descs,
     double sq[3], sp3[3], sS;  // RK4 weighted sums of the q, p and S slopes
     double yq[3], yp[3];
 
-    potential(d, Gk, V, g, K1);
+    potential(d, Gk, V, g, K1, ek);
     {
       const double kp[3] = {-g[0], -g[1], -g[2] - Ek};
       const double kS = 0.5 * (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]) - V - q[2] * Ek;
@@ -107,7 +112,7 @@ __device__ __forceinline__ void run_pack(const Desc* __restrict__ descs,
       }
       sS = kS;
     }
-    potential(d, hRn, yq, V, g, K2);
+    potential(d, hRn, yq, V, g, K2, ek);
     {
       const double kp[3] = {-g[0], -g[1], -g[2] - Eh};
       const double kS = 0.5 * (yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]) - V - yq[2] * Eh;
@@ -121,7 +126,7 @@ __device__ __forceinline__ void run_pack(const Desc* __restrict__ descs,
       }
       sS += 2.0 * kS;
     }
-    potential(d, hRn, yq, V, g, K3);
+    potential(d, hRn, yq, V, g, K3, ek);
     {
       const double kp[3] = {-g[0], -g[1], -g[2] - Eh};
       const double kS = 0.5 * (yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]) - V - yq[2] * Eh;
@@ -135,7 +140,7 @@ __device__ __forceinline__ void run_pack(const Desc* __restrict__ descs,
       }
       sS += 2.0 * kS;
     }
-    potential(d, hRn, yq, V, g, K4);
+    potential(d, hRn, yq, V, g, K4, ek);
     {
       const double kp[3] = {-g[0], -g[1], -g[2] - E1};
       const double kS = 0.5 * (yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]) - V - yq[2] * E1;
@@ -184,7 +189,7 @@ propagate_f64_kernel(const Desc* __restrict__ descs, int n_prob, const double* _
   const int lane = threadIdx.x;
   Pack pk;
   if (!find_pack(e, n_prob, blockIdx.x, lane, pk)) return;
-  run_pack<U>(descs, field, e, dep_from, accum, final_state, capacity, pk, lane, mono);
+  run_pack<U, true>(descs, field, e, dep_from, accum, final_state, capacity, pk, lane, mono);
 }
 
 // Persistent form: a fixed grid of wavefronts pulls pack indices from
@@ -206,7 +211,7 @@ propagate_f64_persistent(const Desc* __restrict__ descs, int n_prob,
     if (idx >= total) break;
     Pack pk;
     find_pack(e, n_prob, queue[idx], lane, pk);
-    run_pack<U>(descs, field, e, dep_from, accum, final_state, capacity, pk, lane, mono);
+    run_pack<U, false>(descs, field, e, dep_from, accum, final_state, capacity, pk, lane, mono);
   }
 }
 
