@@ -411,7 +411,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="measure only the headline FP64 workload")
     ap.add_argument("--serve-requests", type=int, default=120)
-    ap.add_argument("--serve-rate", default="12,14",
+    ap.add_argument("--serve-rate", default="12,16",
                     help="Poisson arrivals per second; a comma list runs one stream per rate")
     args = ap.parse_args()
     if args.gpus != 1:
