@@ -22,11 +22,16 @@ CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC,
           "-Wall", "-Wno-unused-function"]
+# The FP64 trajectory kernels run at an occupancy fixed by their LDS (two
+# wavefronts per SIMD), so the machine scheduler is asked for instruction-level
+# parallelism instead of occupancy (measured 0.65% faster on N2).
+EXTRA = {src: ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]
+         for src in ("propagate_f64.hip", "serve.hip")}
 
 
 def _compile(src, verbose):
     obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *CFLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
