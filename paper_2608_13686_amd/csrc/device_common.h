@@ -130,10 +130,6 @@ __device__ __forceinline__ double exp_neg(double y) {
   q = fma(q, r, 1.0);
   return __builtin_amdgcn_ldexp(q, (int)n);
 }
-__device__ __forceinline__ void exp_neg2_t(double y0, double y1, double& e0, double& e1) {
-  exp_neg2(y0, y1, e0, e1);
-}
-
 // The same constants held in VGPRs for a whole kernel, for kernels with
 // registers to spare: made opaque once (so that the compiler neither folds
 // them back into literals nor rematerialises them), then read by VOP3 FMAs
@@ -213,7 +209,8 @@ __device__ __forceinline__ void sincos_k(double x, double& sn, double& cs) {
   sn = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, s0) ^ ss);
   cs = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, c0) ^ cc);
 }
-__device__ __forceinline__ void exp_neg2_t(float y0, float y1, float& e0, float& e1) {
+// FP32 (mixed kernel): the hardware exponential
+__device__ __forceinline__ void exp_neg2(float y0, float y1, float& e0, float& e1) {
   e0 = __expf(-y0);
   e1 = __expf(-y1);
 }
@@ -301,14 +298,14 @@ __device__ __forceinline__ void potential(const Desc& d, const Geom<T>& G, T& V,
     // is far below a rounding unit of Z_inf
     const T ar0 = PC::alpha(d, 0) * (r2[0] * s[0]), ar1 = PC::alpha(d, 1) * (r2[1] * s[1]);
     if (ar0 < T(kScreenFar) || ar1 < T(kScreenFar)) {
+      const T y0 = fmin(ar0, T(kScreenCap)), y1 = fmin(ar1, T(kScreenCap));
       if constexpr (sizeof(T) == sizeof(double)) {
-        if (ek) {
-          exp_neg2_v(fmin(ar0, T(kScreenCap)), fmin(ar1, T(kScreenCap)), u[0], u[1], *ek);
-        } else {
-          exp_neg2(fmin(ar0, T(kScreenCap)), fmin(ar1, T(kScreenCap)), u[0], u[1]);
-        }
+        if (ek)
+          exp_neg2_v(y0, y1, u[0], u[1], *ek);
+        else
+          exp_neg2(y0, y1, u[0], u[1]);
       } else {
-        exp_neg2_t(fmin(ar0, T(kScreenCap)), fmin(ar1, T(kScreenCap)), u[0], u[1]);
+        exp_neg2(y0, y1, u[0], u[1]);
       }
     }
   }
@@ -351,16 +348,8 @@ __device__ __forceinline__ void potential(const Desc& d, const T hRn[3], const T
   potential(d, G, V, g, K, ek);
 }
 
-// y = K x for the symmetric 3x3 K
-template <typename T>
-__device__ __forceinline__ void symmul(const T K[6], const T x[3], T y[3]) {
-  y[0] = K[0] * x[0] + K[3] * x[1] + K[4] * x[2];
-  y[1] = K[3] * x[0] + K[1] * x[1] + K[5] * x[2];
-  y[2] = K[4] * x[0] + K[5] * x[1] + K[2] * x[2];
-}
-
-// Index of element (r, c) of a symmetric 3x3 matrix in the 6-element storage
-// used by symmul: xx, yy, zz, xy, xz, yz.
+// Index of element (r, c) of a symmetric 3x3 matrix in its 6-element
+// storage: xx, yy, zz, xy, xz, yz.
 __device__ __forceinline__ constexpr int sym_idx(int r, int c) {
   return r == c ? r : (r + c == 1 ? 3 : (r + c == 2 ? 4 : 5));
 }
