@@ -4,8 +4,9 @@
 // Per step, for every live lane: HK prefactor from the monodromy matrix,
 // coherent-state recombination amplitude, wave-reduced Re a added to the
 // dipole accumulator, then one classical RK4 step of (q, p, S) and of the
-// six monodromy columns.  (q, p, S), the HK matrix R and the prefactor live
-// in VGPRs for the whole pulse; the monodromy matrix lives in LDS.
+// six monodromy columns.  (q, p, S), the HK matrix (kept doubled, 2R) and
+// the prefactor live in VGPRs for the whole pulse; the monodromy matrix
+// lives in LDS.
 #include "device_common.h"
 
 namespace sfhk {
