@@ -202,6 +202,32 @@ def timed_plan(sf, probs, n_traj, seeds, precision, tuning, steps, warmup, h_max
     return plan, el / steps
 
 
+def batched_errors(sf, wb, tun, v_mixed):
+    """Relative L2 of the mixed batched dipoles against an FP64 plan of the
+    same trajectories (median and maximum over the problems), as run and with
+    chaotic trajectories filtered by the prefactor cap |C| <= 1e3."""
+    import torch
+
+    def run(probs, precision):
+        pl = sf.Plan(probs, wb["n_traj"], wb["seeds"], precision=precision, tuning=tun,
+                     h_max=40.0)
+        pl.run()
+        torch.cuda.synchronize()
+        out = [pl.v_of(i).clone() for i in range(len(probs))]
+        pl.close()
+        return out
+
+    def summary(a, b):
+        r = np.array([float(torch.linalg.norm(x - y) / torch.linalg.norm(y)) for x, y in zip(a, b)])
+        return {"median": float(np.median(r)), "max": float(r.max()),
+                "worst_problem": wb["problems"][int(r.argmax())]["name"]}
+
+    res = {"rel_l2_vs_fp64": summary(v_mixed, run(wb["problems"], "fp64"))}
+    capped = [dict(p, c_max=1e3) for p in wb["problems"]]
+    res["rel_l2_vs_fp64_prefactor_cap_1e3"] = summary(run(capped, "mixed"), run(capped, "fp64"))
+    return res
+
+
 def saddle_variant(sf, n_traj, steps, warmup):
     """The headline N2 workload with births from the exact SFA saddle point:
     whole step (sampling + propagation + dipole + spectra) and the sampler's
@@ -569,13 +595,16 @@ def main():
         per = live_steps_of(sf, wb["problems"], wb["n_traj"], plan.ens, per_problem=True)
         ls = sum(per)
         bflops = sum(n * flops_per_step(p) for n, p in zip(per, wb["problems"]))
+        v_mixed = [plan.v_of(i).clone() for i in range(len(wb["problems"]))]
+        plan.close()
+        del plan
         variants["batched"] = {"workload": wb["name"], "value": ls / sec,
                                "roofline": step_roofline(bflops, sec),
                                "unit": "trajectory-steps/s", "ms_per_step": sec * 1e3,
                                "live_trajectory_steps": ls, "precision": wb["precision"],
-                               "tuning": list(tun), "launch": "one HIP graph per step"}
-        plan.close()
-        del plan
+                               "tuning": list(tun), "launch": "one HIP graph per step",
+                               "error": batched_errors(sf, wb, tun, v_mixed)}
+        del v_mixed
         torch.cuda.empty_cache()
         variants["small"] = small_variant(sf)
         print(f"small: {variants['small']}", file=sys.stderr, flush=True)

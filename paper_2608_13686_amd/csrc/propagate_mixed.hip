@@ -83,8 +83,7 @@ __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
   double* __restrict__ acc = accum + d.acc_off;
   const int kmin = __builtin_amdgcn_readfirstlane(k0);
   double acc_reg = 0.0;
-  int kend = N + 1;  // first step not run here (FP64 re-run or prefactor cap)
-  int kcap = N + 1;  // step at which the prefactor cap stopped the trajectory
+  int kend = N + 1;  // first step not run here (handed to the FP64 re-run)
 
   for (int kc = kmin; kc <= N; kc += U) {
 #pragma unroll
@@ -110,9 +109,11 @@ __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
       det3c(Rr, Ri, Dr, Di);
       // det R = det R2 / 8 (exact)
       sqrt_continued(0.125 * (double)Dr, 0.125 * (double)Di, Cre, Cim, flips);
-      if (d.c_max2 > 0.0 && Cre * Cre + Cim * Cim > d.c_max2) {
-        kend = k;  // prefactor cap: no contribution from here on
-        kcap = k;
+      if (d.c_max2 > 0.0 && Cre * Cre + Cim * Cim > kMixedCapHandover2 * d.c_max2) {
+        // near the prefactor cap: the FP64 re-run deposits from this step on
+        // and stops the trajectory where the FP64 prefactor reaches the cap
+        kend = k;
+        redo[slot] = k;
         live = false;
       } else {
         const double pd_[3] = {(double)p[0], (double)p[1], (double)p[2]};
@@ -200,7 +201,7 @@ __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
   }
 
   // trajectories handed to the FP64 re-run get their final state from it
-  if (final_state != nullptr && valid && (kend > N || kcap <= N)) {
+  if (final_state != nullptr && valid && kend > N) {
     double* f = final_state + slot;
     const uint64_t st = capacity;
 #pragma unroll

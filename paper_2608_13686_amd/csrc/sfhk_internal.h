@@ -102,6 +102,10 @@ struct PackOut {
 // entry of its FP32 monodromy matrix exceeds this bound (FP32 rounding is
 // then amplified past ~6e-4 relative).
 constexpr float kMixedFlagNorm = 1.0e4f;
+// With a prefactor cap set, it also hands a trajectory over once |C| (from
+// the FP32 monodromy matrix) passes a quarter of the cap, so that the step at
+// which the cap stops the trajectory is decided in FP64, as in the FP64 run.
+constexpr double kMixedCapHandover2 = 1.0 / 16.0;
 
 // launchers (setup_kernels.hip)
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);

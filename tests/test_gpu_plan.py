@@ -128,6 +128,44 @@ def test_plan_mixed_error_vs_fp64(sf):
         assert rel(out["mixed"][i], out["fp64"][i]) < 5e-2
 
 
+def test_batched_workload_full_size(sf, orc):
+    """The batched cos^4 workload at its full size (128 problems x 32,768
+    trajectories) in the benchmark's launch configuration: the FP64 plan
+    against sampled problems run alone and against the oracle, and the mixed
+    plan against the FP64 plan on every problem with chaotic trajectories
+    filtered by the prefactor cap |C| <= 1e3: there the error is that of the
+    FP32 stepping, bounded by 1e-3 (the mixed kernel hands trajectories near
+    the cap to FP64, so both precisions stop them at the same step)."""
+    import torch
+    from paper_2608_13686_amd import autotune
+    wb = workloads.workload_batched(32768)
+    probs, n, seeds = wb["problems"], wb["n_traj"], wb["seeds"]
+    tun = autotune.cached(probs, wb["precision"]) or (1, 8, 1, 1)
+    print(f"{len(probs)} problems x {n[0]}, tuning {tun}", flush=True)
+
+    def plan_v(problems, precision):
+        plan = sf.Plan(problems, n, seeds, precision=precision, tuning=tun, h_max=40.0)
+        plan.run()
+        torch.cuda.synchronize()
+        out = [plan.v_of(i).cpu().numpy() for i in range(len(problems))]
+        plan.close()
+        return out
+
+    v64 = plan_v(probs, "fp64")
+    for i in (0, 45, 64, 127):
+        alone, _ = stepwise(sf, [probs[i]], [n[i]], [seeds[i]], 40.0)
+        print(probs[i]["name"], flush=True)
+        assert rel(v64[i], alone[0]) < 1e-12
+    vo, _, _ = orc.dipole(probs[0], seeds[0], 0, n[0], NTHREADS)
+    assert rel(v64[0], vo) < 1e-10
+    capped = [dict(p, c_max=1e3) for p in probs]
+    c64, cmx = plan_v(capped, "fp64"), plan_v(capped, "mixed")
+    errs = np.array([np.linalg.norm(a - b) / np.linalg.norm(b) for a, b in zip(cmx, c64)])
+    print(f"capped mixed vs FP64 relative L2: median {np.median(errs):.3e}, "
+          f"max {errs.max():.3e} ({probs[int(errs.argmax())]['name']})", flush=True)
+    assert np.all(errs < 1e-3)
+
+
 def test_plan_rejects_bad_tuning(sf):
     probs, n, seeds = batch()
     for bad in [(2, 8, 1, 1), (1, 0 - 1, 1, 1), (1, 8, 3, 1), (1, 64, 1, 1)]:
