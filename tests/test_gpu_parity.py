@@ -315,6 +315,56 @@ def test_full_size_n2_sampled_trajectories_and_linearity(sf, orc):
     assert rel_l2(acc2.cpu().numpy(), acc_full) < 1e-11
 
 
+def test_free_electron_closed_forms_full_size(sf, orc):
+    """The headline workload (2 x 1,048,576 trajectories) with the ion
+    potential switched off, against the Volkov closed forms for every live
+    trajectory (T = its propagation time): M = [[I, T I], [0, I]] (the RK4
+    step matrix is exact for free motion), C = (1 - i gamma T/2)^{3/2} on the
+    continuous branch with no sign flip, p = p0 + A(t_N) - A(t_0) and
+    q = q0 + (p0 - A(t_0) e_z) T + e_z int A dt (RK4 truncation only)."""
+    import torch
+    probs = [workloads.free_problem(workloads.n2(0.0)), workloads.free_problem(workloads.n2(90.0))]
+    n, seeds = [1 << 20, 1 << 20], [1002, 1002]
+    ens, ws = sf.sample_initial(probs, n, seeds)
+    _, fs = sf.propagate(probs, ens, final_state=True, workspace=ws)
+    torch.cuda.synchronize()
+    g = ens_host(ens)
+    fs = fs.cpu().numpy()
+    del ens, ws
+    p = probs[0]
+    N = orc.n_steps(p)
+    t = orc.times(p)
+    _, A = orc.field(p, t)
+    # int_{t_k}^{t_N} A dt for every birth step k: 8-point Gauss-Legendre per step
+    x, wq = np.polynomial.legendre.leggauss(8)
+    h = t[1:] - t[:-1]
+    _, An = orc.field(p, (t[:-1, None] + 0.5 * h[:, None] * (1 + x[None, :])).ravel())
+    seg = 0.5 * h * (An.reshape(-1, 8) @ wq)
+    IA = np.append(np.cumsum(seg[::-1])[::-1], 0.0)
+    live = np.nonzero(g["w"] > 0)[0]
+    assert live.size > 0.3 * sum(n)
+    k0 = g["k0"][live]
+    T = t[N] - t[k0]
+    want = np.tile(np.eye(6).reshape(36, 1), (1, live.size))
+    for a in range(3):
+        want[6 * a + 3 + a] = T
+    err_m = np.max(np.abs(fs[6:42, live] - want) / np.maximum(1.0, T))
+    C = fs[43, live] + 1j * fs[44, live]
+    Cw = np.exp(1.5 * np.log(1 - 0.5j * p["gamma"] * T))
+    err_c = np.max(np.abs(C - Cw) / np.abs(Cw))
+    p0 = np.stack([g["px"], g["py"], g["pz"]])[:, live]
+    q0 = np.stack([g["qx"], g["qy"], g["qz"]])[:, live]
+    pw = p0.copy()
+    pw[2] += A[N] - A[k0]
+    err_p = np.max(np.abs(fs[3:6, live] - pw))
+    qw = q0 + p0 * T
+    qw[2] += IA[k0] - A[k0] * T
+    err_q = np.max(np.abs(fs[0:3, live] - qw) / np.maximum(1.0, np.abs(qw)))
+    print(f"{live.size} live: M {err_m:.2e}, C {err_c:.2e}, p {err_p:.2e}, q {err_q:.2e}", flush=True)
+    assert err_m < 1e-11 and err_c < 1e-12 and err_p < 1e-10 and err_q < 1e-8
+    assert np.all(fs[45, live] == 0)
+
+
 @pytest.mark.parametrize("precision", ["fp64"])
 def test_prefactor_cap_matches_oracle(sf, orc, precision):
     """The optional prefactor cap: contributions stop at the first step with
