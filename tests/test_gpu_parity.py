@@ -365,6 +365,59 @@ def test_free_electron_closed_forms_full_size(sf, orc):
     assert np.all(fs[45, live] == 0)
 
 
+def test_symplectic_monodromy_full_size(sf, orc):
+    """The headline N2 workload at full size: symplecticity of the final
+    monodromy matrix of every live trajectory with |M| <= 1e4.  det M = 1 to
+    1e-7 |M|^2 and |det R| >= 1 for all of them.  RK4 is not symplectic: the
+    defect |M^T J M - J| / |M|^2 is at the rounding level for most
+    trajectories (median) and grows on close passes by a nucleus, where the
+    per-step defect O(h^5 |d^k F|) is large; the trajectories with the largest
+    defects are run by the oracle, whose M must equal the kernel's (to the
+    final-state tolerance), so the defect is the integrator's, not the
+    kernel's.  Beyond |M| = 1e4 (chaotic trajectories, |M| up to ~1e26 here)
+    det M is lost to rounding."""
+    import torch
+    probs = [workloads.n2(0.0), workloads.n2(90.0)]
+    n, seeds = [1 << 20, 1 << 20], [1002, 1002]
+    ens, ws = sf.sample_initial(probs, n, seeds)
+    _, fs = sf.propagate(probs, ens, final_state=True, workspace=ws)
+    torch.cuda.synchronize()
+    g = ens_host(ens)
+    fs = fs.cpu().numpy()
+    del ens, ws
+    live = np.nonzero(g["w"] > 0)[0]
+    M = np.ascontiguousarray(fs[6:42, live].T).reshape(-1, 6, 6)
+    J = np.block([[np.zeros((3, 3)), np.eye(3)], [-np.eye(3), np.zeros((3, 3))]])
+    nm2 = np.linalg.norm(M, ord=2, axis=(1, 2)) ** 2
+    reg = np.nonzero(nm2 <= 1e8)[0]
+    M, nm2 = M[reg], nm2[reg]
+    err_j = np.max(np.abs(np.transpose(M, (0, 2, 1)) @ J @ M - J), axis=(1, 2)) / nm2
+    err_d = np.abs(np.linalg.det(M) - 1) / nm2
+    gam = probs[0]["gamma"]
+    R = 0.5 * (M[:, :3, :3] + M[:, 3:, 3:] - 1j * gam * M[:, :3, 3:] + 1j / gam * M[:, 3:, :3])
+    absdet = np.abs(np.linalg.det(R))
+    print(f"{live.size} live, {reg.size} with |M| <= 1e4: |M^T J M - J|/|M|^2 median "
+          f"{np.median(err_j):.2e}, max {err_j.max():.2e}; |det M - 1|/|M|^2 max "
+          f"{err_d.max():.2e}; min |det R| {absdet.min():.6g}", flush=True)
+    assert reg.size > 0.95 * live.size
+    assert np.median(err_j) < 1e-12
+    assert err_d.max() < 1e-7 and absdet.min() >= 1 - 1e-6
+    for j in np.argsort(err_j)[-4:]:
+        i = live[reg[j]]
+        p = probs[int(g["prob"][i])]
+        _, fo = orc.trajectory(p, int(g["k0"][i]), (g["qx"][i], g["qy"][i], g["qz"][i]),
+                               (g["px"][i], g["py"][i], g["pz"][i]),
+                               (g["nx"][i], g["ny"][i], g["nz"][i]), g["w"][i], amplitudes=False)
+        Mo = fo[6:42].reshape(6, 6)
+        amp = 1.0 + np.linalg.norm(Mo, 2)
+        tol = 1e-14 * amp * math.sqrt(orc.n_steps(p) - int(g["k0"][i]) + 1) * 100
+        err_o = np.max(np.abs(Mo.T @ J @ Mo - J)) / np.linalg.norm(Mo, 2) ** 2
+        diff = np.max(np.abs(fs[6:42, i] - fo[6:42])) / amp
+        print(f"slot {i}: defect {err_j[j]:.3e} (oracle {err_o:.3e}), |M - M_oracle|/|M| {diff:.2e}",
+              flush=True)
+        assert diff < tol
+
+
 @pytest.mark.parametrize("precision", ["fp64"])
 def test_prefactor_cap_matches_oracle(sf, orc, precision):
     """The optional prefactor cap: contributions stop at the first step with
