@@ -235,6 +235,77 @@ def test_edge_cases(sf, orc):
     assert s["k0"].max() <= orc.n_steps(p) - 1
 
 
+def gto_table_64():
+    """64 primitives, 32 per centre, s and p in pairs sharing an exponent
+    (32 recombination shells), gerade (p coefficients change sign between
+    the centres), exponents 0.08..~9 and O(1) coefficients."""
+    rng = np.random.default_rng(64)
+    out = []
+    for c in (0, 1):
+        for j in range(32):
+            l = j % 2
+            a = 0.08 * 1.35 ** (j // 2)
+            coef = float(rng.uniform(0.2, 1.0)) * (1 if l == 0 or c == 0 else -1)
+            out.append((c, l, a, coef))
+    return out
+
+
+def test_maximum_sizes(sf, orc):
+    """The ABI's largest tables: a 64-primitive GTO expansion (the maximum)
+    against the oracle, and the maximum number of problems in one call
+    (65,535 H2 problems of one trajectory each, alignment and seed varying)
+    with sampled problems against the oracle.  A one-trajectory dipole carries
+    that trajectory's rounding amplification, so its bound is the
+    per-trajectory one, growing with |M| (as for the final states), plus the
+    stated bound of the kernels' far-field recombination cut: a skipped shell
+    term is below e^-45 * 1e4 of an O(1) amplitude, at most 2 w n_shell of
+    them per sample of a one-trajectory dipole (v = 2 accum / n).  For a
+    trajectory that never comes back near the core those terms are the whole
+    dipole (|v| ~ 1e-17 w), which an ensemble never notices."""
+    import torch
+    p = workloads.h2_softcore(30.0)
+    p["target"]["gto"] = gto_table_64()
+    assert len(p["target"]["gto"]) == 64
+    (v,), _ = gpu_dipole(sf, [p], [600], [1001])
+    vo, _, _ = orc.dipole(p, 1001, 0, 600, NTHREADS)
+    assert np.linalg.norm(vo) > 0
+    assert rel_l2(v, vo) < REL_L2
+
+    n_prob = 65535
+    probs = [workloads.h2_softcore(float(i % 91)) for i in range(n_prob)]
+    n, seeds = [1] * n_prob, list(range(n_prob))
+    ens, ws = sf.sample_initial(probs, n, seeds)
+    acc, fs = sf.propagate(probs, ens, final_state=True, workspace=ws)
+    v = sf.dipole(probs, acc, n)
+    torch.cuda.synchronize()
+    w = ens.w.cpu().numpy()
+    k0 = ens.k0.cpu().numpy()
+    assert w.size >= n_prob
+    offs, lens = sf.accum_layout(probs)
+    live = np.nonzero(w[:n_prob] > 0)[0]
+    dead = np.nonzero(w[:n_prob] == 0)[0]
+    print(f"{n_prob} problems, {live.size} with a live trajectory", flush=True)
+    assert live.size > 100 and dead.size > 0
+    rng = np.random.default_rng(7)
+    picks = list(rng.choice(live, size=6, replace=False)) + [int(live[-1]), int(dead[-1])]
+    for i in picks:
+        # one trajectory per problem: slot i belongs to problem i
+        vg = v[offs[i]:offs[i] + lens[i]].cpu().numpy()
+        vo, _, _ = orc.dipole(probs[i], seeds[i], 0, 1, 1)
+        if w[i] == 0:
+            assert np.all(vg == 0) and np.all(vo == 0)
+            continue
+        amp = 1.0 + np.linalg.norm(fs[6:42, i].cpu().numpy().reshape(6, 6), 2)
+        steps = orc.n_steps(probs[i]) - int(k0[i]) + 1
+        tol = max(REL_L2, 1e-14 * amp * math.sqrt(steps) * 100)
+        n_shell = len({(g[0], g[2]) for g in probs[i]["target"]["gto"]})
+        floor = 2.0 * w[i] * n_shell * math.exp(-45.0) * 1e4 * math.sqrt(vg.size)
+        err = float(np.linalg.norm(vg - vo))
+        print(f"problem {i}: |M| + 1 = {amp:.3g}, |v| {np.linalg.norm(vo):.3e}, error {err:.3e}, "
+              f"bound {tol:.2e} |v| + {floor:.2e}", flush=True)
+        assert err <= tol * np.linalg.norm(vo) + floor, i
+
+
 def test_stretched_molecule_screening(sf, orc):
     """N2 stretched to R = 20 a.u.: near one centre the other centre's
     screening exponent lies beyond the cut-off (alpha rho up to ~93), so the
