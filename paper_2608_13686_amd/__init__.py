@@ -272,16 +272,34 @@ class Plan:
             C.c_void_p(self.V_im.data_ptr()), C.c_void_p(self.yield_.data_ptr()),
             _stream(stream), C.byref(h)), "sfhk_plan_create")
         self._h = h
+        self._streams = set()
+
+    def _buffers(self):
+        yield from (getattr(self.ens, f) for f in self.ens.FIELDS_I32 + self.ens.FIELDS_F64 +
+                    ("order", "live_start", "live_count", "pack_start"))
+        yield from (self.workspace, self.accum, self.v, self.V_re, self.V_im, self.yield_)
+
+    def _on(self, stream):
+        """The plan's buffers are allocated on the current stream: work on
+        another stream is recorded with the allocator, so that freeing the
+        plan while that work is in flight cannot hand its memory to a new
+        tensor."""
+        if stream is not None and stream != torch.cuda.current_stream() and \
+                stream.cuda_stream not in self._streams:
+            for t in self._buffers():
+                t.record_stream(stream)
+            self._streams.add(stream.cuda_stream)
+        return _stream(stream)
 
     def run(self, stream=None):
-        _abi.check(_abi.lib().sfhk_plan_run(self._h, _stream(stream)), "sfhk_plan_run")
+        _abi.check(_abi.lib().sfhk_plan_run(self._h, self._on(stream)), "sfhk_plan_run")
 
     def capture(self, stream):
         """Record run() into a HIP graph on a non-default torch stream."""
-        _abi.check(_abi.lib().sfhk_plan_capture(self._h, _stream(stream)), "sfhk_plan_capture")
+        _abi.check(_abi.lib().sfhk_plan_capture(self._h, self._on(stream)), "sfhk_plan_capture")
 
     def replay(self, stream=None):
-        _abi.check(_abi.lib().sfhk_plan_replay(self._h, _stream(stream)), "sfhk_plan_replay")
+        _abi.check(_abi.lib().sfhk_plan_replay(self._h, self._on(stream)), "sfhk_plan_replay")
 
     @property
     def V(self):

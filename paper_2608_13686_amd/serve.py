@@ -113,6 +113,13 @@ class HipExecutor:
         self.n_groups = int(n_groups)
         self.group_streams = [self.stream] + [torch.cuda.Stream(device=device)
                                               for _ in range(self.n_groups - 1)]
+        # the pool and the table are allocated on the current stream: work on
+        # the other streams is recorded with the allocator, so that dropping
+        # the executor while a window is in flight cannot reuse their memory
+        for gs in self.group_streams:
+            if gs != torch.cuda.current_stream():
+                self.pool.record_stream(gs)
+                self.table.record_stream(gs)
 
     def footprint(self, problem, n_traj):
         arr = _abi.make_problems([problem])
