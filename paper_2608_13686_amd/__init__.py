@@ -5,6 +5,7 @@ torch stream is the HIP stream, and every step runs in the library's HIP
 kernels.  The names follow the C ABI in ``include/sfhk.h``.
 """
 import ctypes as C
+import functools
 import math
 
 import torch
@@ -26,6 +27,23 @@ def abi_version():
 def _stream(stream):
     s = torch.cuda.current_stream() if stream is None else stream
     return C.c_void_p(s.cuda_stream)
+
+
+def _on_stream(fn):
+    """Run a step on ``stream`` (if given): the stream first waits for the
+    work already queued on torch's current stream (which made the inputs),
+    and the step runs with ``stream`` as torch's current stream, so that the
+    tensors it allocates, zeroes or combines are ordered with the library's
+    kernels there.  The outputs are ready on ``stream``: a caller using them
+    on another stream synchronises the two, as usual in torch."""
+    @functools.wraps(fn)
+    def wrapper(*args, stream=None, **kw):
+        if stream is None:
+            return fn(*args, **kw)
+        stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(stream):
+            return fn(*args, stream=stream, **kw)
+    return wrapper
 
 
 def problem_steps(prob):
@@ -84,6 +102,7 @@ class Ensemble:
         return s
 
 
+@_on_stream
 def sample_initial(probs, n_per_prob, seeds, first_index=None, ens=None, workspace=None,
                    stream=None, device="cuda"):
     """Sample and pack an ensemble; returns (Ensemble, workspace tensor)."""
@@ -107,6 +126,7 @@ def sample_initial(probs, n_per_prob, seeds, first_index=None, ens=None, workspa
     return ens, workspace
 
 
+@_on_stream
 def propagate(probs, ens, precision="fp64", accum=None, final_state=False, workspace=None,
               stream=None):
     """Propagate the ensemble and add sum_j Re a_jk into accum (created zeroed
@@ -133,6 +153,7 @@ def propagate(probs, ens, precision="fp64", accum=None, final_state=False, works
     return accum, fs
 
 
+@_on_stream
 def dipole(probs, accum, n_sampled, v_out=None, stream=None):
     """v_k = (2/N_s) accum_k per problem."""
     arr = _abi.make_problems(probs)
@@ -144,6 +165,7 @@ def dipole(probs, accum, n_sampled, v_out=None, stream=None):
     return v_out
 
 
+@_on_stream
 def spectrum(v, t_first, dt, tau_H, omega, stream=None):
     """(V complex128 tensor, yield) of the Hanning-windowed transform (Eq. 3)."""
     v = v.contiguous()
@@ -159,6 +181,7 @@ def spectrum(v, t_first, dt, tau_H, omega, stream=None):
     return torch.complex(Vr, Vi), Y
 
 
+@_on_stream
 def return_steps(probs, ens, r_return=4.0, workspace=None, stream=None):
     """(k_ret int32, e_ret) per slot: first return step into |q| < r_return
     (-1 if none) and the kinetic energy there (sfhk_return_steps)."""
@@ -180,6 +203,7 @@ def return_steps(probs, ens, r_return=4.0, workspace=None, stream=None):
     return k_ret, e_ret
 
 
+@_on_stream
 def gabor(v, t_first, dt, sigma, t_c, omega, stream=None):
     """(G complex128 [n_c, n_omega], yield) of the Gaussian-window transform
     (sfhk_gabor) of v at window centres t_c and frequencies omega."""
@@ -209,6 +233,7 @@ def harmonic_grid(prob, h_max, h_step=0.05):
     return torch.arange(n, dtype=torch.float64) * h_step * omega0
 
 
+@_on_stream
 def run(probs, n_traj, seeds, precision="fp64", h_max=40.0, h_step=0.05, device="cuda",
         stream=None):
     """Whole path for a list of problems: sample, propagate, dipole and the
@@ -263,6 +288,7 @@ class Plan:
         t = _abi.Tuning(*(tuning or (0, 8, 1, 1)))
         es = self.ens.struct()
         h = C.c_void_p()
+        self._streams = set()
         _abi.check(L.sfhk_plan_create(
             self._arr, n_prob, _abi.u64_array(self.n_traj), _abi.u64_array(seeds),
             _abi.u64_array(self.first_index), PRECISION[precision], C.byref(t), float(h_step),
@@ -270,9 +296,8 @@ class Plan:
             self.workspace.numel(), C.c_void_p(self.accum.data_ptr()),
             C.c_void_p(self.v.data_ptr()), C.c_void_p(self.V_re.data_ptr()),
             C.c_void_p(self.V_im.data_ptr()), C.c_void_p(self.yield_.data_ptr()),
-            _stream(stream), C.byref(h)), "sfhk_plan_create")
+            self._on(stream), C.byref(h)), "sfhk_plan_create")
         self._h = h
-        self._streams = set()
 
     def _buffers(self):
         yield from (getattr(self.ens, f) for f in self.ens.FIELDS_I32 + self.ens.FIELDS_F64 +
@@ -280,15 +305,17 @@ class Plan:
         yield from (self.workspace, self.accum, self.v, self.V_re, self.V_im, self.yield_)
 
     def _on(self, stream):
-        """The plan's buffers are allocated on the current stream: work on
-        another stream is recorded with the allocator, so that freeing the
-        plan while that work is in flight cannot hand its memory to a new
-        tensor."""
-        if stream is not None and stream != torch.cuda.current_stream() and \
-                stream.cuda_stream not in self._streams:
-            for t in self._buffers():
-                t.record_stream(stream)
-            self._streams.add(stream.cuda_stream)
+        """The plan's buffers are allocated and initialised on the current
+        stream: work on another stream first waits for the current stream,
+        and is recorded with the allocator, so that freeing the plan while
+        that work is in flight cannot hand its memory to a new tensor."""
+        cur = torch.cuda.current_stream()
+        if stream is not None and stream != cur:
+            stream.wait_stream(cur)
+            if stream.cuda_stream not in self._streams:
+                for t in self._buffers():
+                    t.record_stream(stream)
+                self._streams.add(stream.cuda_stream)
         return _stream(stream)
 
     def run(self, stream=None):

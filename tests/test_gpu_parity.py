@@ -166,6 +166,27 @@ def gpu_dipole(sf, probs, n, seeds, first=None):
     return [v[o:o + l].cpu().numpy() for o, l in zip(offs, lens)], acc.cpu().numpy()
 
 
+def test_steps_on_a_side_stream(sf):
+    """The step-wise path on a non-current stream, with unrelated work in
+    flight on the current one, reproduces the current-stream result (the
+    accumulator's zero fill and the spectra's outputs are ordered with the
+    library's kernels on that stream)."""
+    import torch
+    probs = [workloads.h2_softcore(), workloads.n2(30.0)]
+    n, seeds = [2000, 1000], [1001, 5]
+    ref = sf.run(probs, n, seeds, h_max=30.0)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    for r in range(3):
+        junk = torch.randn(1 << 22, device="cuda").cumsum(0)
+        out = sf.run(probs, n, seeds, h_max=30.0, stream=side)
+        side.synchronize()
+        for i in range(len(probs)):
+            assert rel_l2(out["v"][i].cpu().numpy(), ref["v"][i].cpu().numpy()) < 1e-12, r
+            assert rel_l2(out["yield"][i].cpu().numpy(), ref["yield"][i].cpu().numpy()) < 1e-11, r
+        del junk
+
+
 def test_dipole_h2_full_workload(sf, orc):
     """The H2 soft-core workload in full: 4096 trajectories, seed 1001."""
     p = workloads.h2_softcore()
