@@ -170,3 +170,31 @@ def test_gabor_arguments_validated(L):
     assert lib.sfhk_gabor(*args(ptr=None)) == 1
     assert lib.sfhk_gabor(*args(n_c=0)) == 0
     assert lib.sfhk_gabor(*args(n_w=0)) == 0
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without the built library every step raises: the product path has no
+    CPU fallback."""
+    from paper_2608_13686_amd import _abi
+    import paper_2608_13686_amd as sf
+    monkeypatch.setattr(_abi, "LIB_PATH", os.path.join(ROOT, "_missing", "libsfhk.so"))
+    monkeypatch.setattr(_abi, "_lib", None)
+    with pytest.raises(ImportError):
+        sf.problem_steps(workloads.h2_softcore())
+    with pytest.raises(ImportError):
+        sf.workspace_bytes([workloads.h2_softcore()], 16)
+    with pytest.raises(ImportError):
+        sf.abi_version()
+
+
+def test_package_never_touches_the_oracle():
+    """No source of the package (binding, kernels, server, tuner) names the
+    oracle: it is test infrastructure only."""
+    pkg = os.path.join(ROOT, "paper_2608_13686_amd")
+    seen = 0
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp", ".c")):
+                seen += 1
+                assert "oracle" not in open(os.path.join(dirpath, f)).read().lower(), f
+    assert seen > 10
