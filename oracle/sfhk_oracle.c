@@ -43,6 +43,7 @@ void orc_laser(const orc_problem* P, double* omega, double* E0, double* tau, int
   if (N) *N = P->n_steps > 0 ? P->n_steps : (int32_t)lround(T / P->dt);
 }
 
+/* The step grid of the same reading: t_k = -tau/2 + k dt, k = 0..N. */
 double orc_time(const orc_problem* P, int32_t k) {
   double tau;
   orc_laser(P, NULL, NULL, &tau, NULL);
@@ -535,6 +536,7 @@ static void sample_one(const orc_problem* P, uint64_t seed, uint64_t j, int32_t 
   *w = ww;
 }
 
+/* Trajectories first .. first + n - 1 of a problem, each drawn as above. */
 void orc_sample(const orc_problem* P, uint64_t seed, uint64_t first, uint64_t n, int32_t* k0,
                 double* q0, double* p0, double* nax, double* w, double* dph) {
   double E0;
@@ -577,7 +579,11 @@ static void rhs(const orc_problem* P, const double n[3], double E, const double 
   f[42] = 0.5 * (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]) - V - y[2] * E;
 }
 
-/* classical fourth-order Runge-Kutta from t_k to t_{k+1} = t_k + dt */
+/* Classical fourth-order Runge-Kutta from t_k to t_{k+1} = t_k + dt for the
+ * whole 43-component state (Hamilton's equations of Sec. II.A with the
+ * monodromy and the action); the paper states no integrator for the
+ * trajectories (it uses this scheme for the TDSE of Sec. II.D), so this is a
+ * reading, with the field at t_k, t_k + dt/2 and t_{k+1}. */
 static void rk4_step(const orc_problem* P, const double n[3], int32_t k, double y[NY]) {
   double h = P->dt;
   double tk = orc_time(P, k);
@@ -651,6 +657,7 @@ static int traj_core(const orc_problem* P, int32_t k0, int32_t k_end, const doub
   return 0;
 }
 
+/* One trajectory from its birth step k0 to k_end (Sec. II.A), as above. */
 int orc_trajectory(const orc_problem* P, int32_t k0, int32_t k_end, const double q0[3],
                    const double p0[3], const double nax[3], double w, double dph,
                    double* amp_re, double* amp_im, double* c_re, double* c_im,
