@@ -25,7 +25,7 @@ CANDIDATES = [(0, 8, u, 1) for u in (1, 2, 4)] + [(1, w, u, 1) for w in (4, 8, 1
 
 
 def cache_key(probs, precision):
-    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
     kinds = sorted({"screened" if any(c["dZ"] != 0 for c in p["target"]["centers"])
                     else "softcore" for p in probs})
     prims = sorted({len(p["target"]["gto"]) for p in probs})
