@@ -205,7 +205,8 @@ def timed_plan(sf, probs, n_traj, seeds, precision, tuning, steps, warmup, h_max
 def batched_errors(sf, wb, tun, v_mixed):
     """Relative L2 of the mixed batched dipoles against an FP64 plan of the
     same trajectories (median and maximum over the problems), as run and with
-    chaotic trajectories filtered by the prefactor cap |C| <= 1e3."""
+    the prefactor cap |C| <= 1e3 (near the cap the mixed run hands
+    trajectories to FP64, so with this cap both runs are mostly FP64)."""
     import torch
 
     def run(probs, precision):
@@ -436,10 +437,17 @@ def main():
                     help="run one plain device copy of this size first (calibrates HBM counters)")
     ap.add_argument("--no-variants", action="store_true",
                     help="measure only the headline FP64 workload")
+    ap.add_argument("--only", default="",
+                    help="comma list of variants to run (mixed, batched, small, analysis, "
+                         "saddle, averaging, served); default all")
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--serve-rate", default="12,16",
                     help="Poisson arrivals per second; a comma list runs one stream per rate")
     args = ap.parse_args()
+    only = {x for x in args.only.split(",") if x}
+    unknown = only - {"mixed", "batched", "small", "analysis", "saddle", "averaging", "served"}
+    if unknown:
+        sys.exit(f"unknown variants: {sorted(unknown)}")
     if args.gpus != 1:
         print("bench.py measures one GPU: the path shards by trajectory index with one "
               "dipole reduction per problem, but only the single-GPU path is built; "
@@ -548,75 +556,84 @@ def main():
     if not args.no_variants:
         from paper_2608_13686_amd import autotune
         variants = {}
-        # mixed precision on the same trajectories, error against the FP64 run
-        v64 = v.clone()
-        tun = autotune.cached(probs, "mixed") or (0, 8, 1, 1)
-        plan, sec = timed_plan(sf, probs, n_traj, seeds, "mixed", tun, args.steps, args.warmup,
-                               100.0)
-        errs = []
-        for i, (p, o, l) in enumerate(zip(probs, offs, lens)):
-            rel = float(torch.linalg.norm(plan.v_of(i) - v64[o:o + l]) /
-                        torch.linalg.norm(v64[o:o + l]))
-            med, p90 = spectral_db(sf, p, plan.v_of(i), v64[o:o + l], 15.0, 80.0)
-            errs.append({"theta_deg": round(math.degrees(p["align"]["theta"]), 3),
-                         "rel_l2_vs_fp64": rel, "spectral_db_median_H15_80": med,
-                         "spectral_db_p90_H15_80": p90})
-        plan.close()
-        del plan
-        # the same comparison with chaotic trajectories filtered by the prefactor
-        # cap |C| <= 1e3: the error of the FP32 stepping itself
-        capped = [dict(p, c_max=1e3) for p in probs]
-        errs_c = []
-        pf = sf.Plan(capped, n_traj, seeds, precision="fp64", tuning=tun, h_max=100.0)
-        pm = sf.Plan(capped, n_traj, seeds, precision="mixed", tuning=tun, h_max=100.0)
-        pf.run()
-        pm.run()
-        torch.cuda.synchronize()
-        for i, p in enumerate(capped):
-            rel = float(torch.linalg.norm(pm.v_of(i) - pf.v_of(i)) / torch.linalg.norm(pf.v_of(i)))
-            med, p90 = spectral_db(sf, p, pm.v_of(i), pf.v_of(i), 15.0, 80.0)
-            errs_c.append({"theta_deg": round(math.degrees(p["align"]["theta"]), 3),
-                           "rel_l2_vs_fp64": rel, "spectral_db_median_H15_80": med,
-                           "spectral_db_p90_H15_80": p90})
-        pf.close()
-        pm.close()
-        del pf, pm
-        variants["mixed"] = {"workload": wl["name"], "value": live_steps / sec,
-                             "unit": "trajectory-steps/s", "ms_per_step": sec * 1e3,
-                             "tuning": list(tun), "error_vs_fp64": errs,
-                             "error_vs_fp64_prefactor_cap_1e3": errs_c,
-                             "speedup_vs_fp64": (el / args.steps) / sec,
-                             "roofline": step_roofline(algo_flops, sec)}
-        # batched cos^4 H2 + N2 over 64 lasers each, persistent plan, graph replay
-        wb = workloads.workload_batched(32768)
-        tun = autotune.cached(wb["problems"], wb["precision"]) or (1, 8, 1, 1)
-        plan, sec = timed_plan(sf, wb["problems"], wb["n_traj"], wb["seeds"], wb["precision"],
-                               tun, args.steps, args.warmup, 40.0)
-        per = live_steps_of(sf, wb["problems"], wb["n_traj"], plan.ens, per_problem=True)
-        ls = sum(per)
-        bflops = sum(n * flops_per_step(p) for n, p in zip(per, wb["problems"]))
-        v_mixed = [plan.v_of(i).clone() for i in range(len(wb["problems"]))]
-        plan.close()
-        del plan
-        variants["batched"] = {"workload": wb["name"], "value": ls / sec,
-                               "roofline": step_roofline(bflops, sec),
-                               "unit": "trajectory-steps/s", "ms_per_step": sec * 1e3,
-                               "live_trajectory_steps": ls, "precision": wb["precision"],
-                               "tuning": list(tun), "launch": "one HIP graph per step",
-                               "error": batched_errors(sf, wb, tun, v_mixed)}
-        del v_mixed
+        def want(name):
+            return not only or name in only
+        if want("mixed"):
+            # mixed precision on the same trajectories, error against the FP64 run
+            v64 = v.clone()
+            tun = autotune.cached(probs, "mixed") or (0, 8, 1, 1)
+            plan, sec = timed_plan(sf, probs, n_traj, seeds, "mixed", tun, args.steps, args.warmup,
+                                   100.0)
+            errs = []
+            for i, (p, o, l) in enumerate(zip(probs, offs, lens)):
+                rel = float(torch.linalg.norm(plan.v_of(i) - v64[o:o + l]) /
+                            torch.linalg.norm(v64[o:o + l]))
+                med, p90 = spectral_db(sf, p, plan.v_of(i), v64[o:o + l], 15.0, 80.0)
+                errs.append({"theta_deg": round(math.degrees(p["align"]["theta"]), 3),
+                             "rel_l2_vs_fp64": rel, "spectral_db_median_H15_80": med,
+                             "spectral_db_p90_H15_80": p90})
+            plan.close()
+            del plan
+            # the same comparison with the prefactor cap |C| <= 1e3 (chaotic
+            # trajectories filtered; the mixed run hands trajectories near the
+            # cap to FP64, so with this cap both runs are mostly FP64)
+            capped = [dict(p, c_max=1e3) for p in probs]
+            errs_c = []
+            pf = sf.Plan(capped, n_traj, seeds, precision="fp64", tuning=tun, h_max=100.0)
+            pm = sf.Plan(capped, n_traj, seeds, precision="mixed", tuning=tun, h_max=100.0)
+            pf.run()
+            pm.run()
+            torch.cuda.synchronize()
+            for i, p in enumerate(capped):
+                rel = float(torch.linalg.norm(pm.v_of(i) - pf.v_of(i)) / torch.linalg.norm(pf.v_of(i)))
+                med, p90 = spectral_db(sf, p, pm.v_of(i), pf.v_of(i), 15.0, 80.0)
+                errs_c.append({"theta_deg": round(math.degrees(p["align"]["theta"]), 3),
+                               "rel_l2_vs_fp64": rel, "spectral_db_median_H15_80": med,
+                               "spectral_db_p90_H15_80": p90})
+            pf.close()
+            pm.close()
+            del pf, pm
+            variants["mixed"] = {"workload": wl["name"], "value": live_steps / sec,
+                                 "unit": "trajectory-steps/s", "ms_per_step": sec * 1e3,
+                                 "tuning": list(tun), "error_vs_fp64": errs,
+                                 "error_vs_fp64_prefactor_cap_1e3": errs_c,
+                                 "speedup_vs_fp64": (el / args.steps) / sec,
+                                 "roofline": step_roofline(algo_flops, sec)}
+        if want("batched"):
+            # batched cos^4 H2 + N2 over 64 lasers each, persistent plan, graph replay
+            wb = workloads.workload_batched(32768)
+            tun = autotune.cached(wb["problems"], wb["precision"]) or (1, 8, 1, 1)
+            plan, sec = timed_plan(sf, wb["problems"], wb["n_traj"], wb["seeds"], wb["precision"],
+                                   tun, args.steps, args.warmup, 40.0)
+            per = live_steps_of(sf, wb["problems"], wb["n_traj"], plan.ens, per_problem=True)
+            ls = sum(per)
+            bflops = sum(n * flops_per_step(p) for n, p in zip(per, wb["problems"]))
+            v_mixed = [plan.v_of(i).clone() for i in range(len(wb["problems"]))]
+            plan.close()
+            del plan
+            variants["batched"] = {"workload": wb["name"], "value": ls / sec,
+                                   "roofline": step_roofline(bflops, sec),
+                                   "unit": "trajectory-steps/s", "ms_per_step": sec * 1e3,
+                                   "live_trajectory_steps": ls, "precision": wb["precision"],
+                                   "tuning": list(tun), "launch": "one HIP graph per step",
+                                   "error": batched_errors(sf, wb, tun, v_mixed)}
+            del v_mixed
         torch.cuda.empty_cache()
-        variants["small"] = small_variant(sf)
-        print(f"small: {variants['small']}", file=sys.stderr, flush=True)
-        variants["analysis"] = analysis_variant(sf, probs, ens, ws, v, offs, lens)
-        print(f"analysis: {variants['analysis']}", file=sys.stderr, flush=True)
-        variants["saddle"] = saddle_variant(sf, args.n_traj, args.steps, args.warmup)
-        print(f"saddle: {variants['saddle']}", file=sys.stderr, flush=True)
-        torch.cuda.empty_cache()
-        variants["averaging"] = averaging_variant(sf)
-        print(f"averaging: {variants['averaging']}", file=sys.stderr, flush=True)
-        torch.cuda.empty_cache()
-        if args.serve_requests > 0:
+        if want("small"):
+            variants["small"] = small_variant(sf)
+            print(f"small: {variants['small']}", file=sys.stderr, flush=True)
+        if want("analysis"):
+            variants["analysis"] = analysis_variant(sf, probs, ens, ws, v, offs, lens)
+            print(f"analysis: {variants['analysis']}", file=sys.stderr, flush=True)
+        if want("saddle"):
+            variants["saddle"] = saddle_variant(sf, args.n_traj, args.steps, args.warmup)
+            print(f"saddle: {variants['saddle']}", file=sys.stderr, flush=True)
+            torch.cuda.empty_cache()
+        if want("averaging"):
+            variants["averaging"] = averaging_variant(sf)
+            print(f"averaging: {variants['averaging']}", file=sys.stderr, flush=True)
+            torch.cuda.empty_cache()
+        if want("served") and args.serve_requests > 0:
             rates = [float(r) for r in str(args.serve_rate).split(",") if r]
             for i, res in enumerate(served_variant(sf, args.serve_requests, rates)):
                 variants["served" if i == 0 else f"served_{rates[i]:g}hz"] = res

@@ -14,3 +14,13 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
     assert '"metric"' not in r.stdout
+
+
+def test_unknown_variant_is_refused():
+    """--only names variants; an unknown name stops the bench before any
+    device work."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--only", "mixed,bogus"],
+                       capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert r.returncode != 0
+    assert "unknown variants: ['bogus']" in r.stderr
+    assert '"metric"' not in r.stdout
