@@ -202,11 +202,20 @@ def timed_plan(sf, probs, n_traj, seeds, precision, tuning, steps, warmup, h_max
     return plan, el / steps
 
 
+def chaos_cap(sf, p):
+    """Prefactor cap for the error diagnostic: five times the free-spreading
+    |C| = |1 - i gamma tau/2|^{3/2} of a trajectory that lives the whole
+    pulse, so that regular trajectories stay below the mixed kernel's
+    hand-over threshold (c_max/4) and only chaotic ones are cut."""
+    _, _, tau = sf.problem_steps(p)
+    return 5.0 * abs(1.0 - 0.5j * p["gamma"] * tau) ** 1.5
+
+
 def batched_errors(sf, wb, tun, v_mixed):
     """Relative L2 of the mixed batched dipoles against an FP64 plan of the
     same trajectories (median and maximum over the problems), as run and with
-    the prefactor cap |C| <= 1e3 (near the cap the mixed run hands
-    trajectories to FP64, so with this cap both runs are mostly FP64)."""
+    chaotic trajectories cut by the prefactor cap chaos_cap (the FP32
+    stepping error of the regular ones)."""
     import torch
 
     def run(probs, precision):
@@ -224,8 +233,9 @@ def batched_errors(sf, wb, tun, v_mixed):
                 "worst_problem": wb["problems"][int(r.argmax())]["name"]}
 
     res = {"rel_l2_vs_fp64": summary(v_mixed, run(wb["problems"], "fp64"))}
-    capped = [dict(p, c_max=1e3) for p in wb["problems"]]
-    res["rel_l2_vs_fp64_prefactor_cap_1e3"] = summary(run(capped, "mixed"), run(capped, "fp64"))
+    capped = [dict(p, c_max=chaos_cap(sf, p)) for p in wb["problems"]]
+    res["rel_l2_vs_fp64_chaos_cap"] = summary(run(capped, "mixed"), run(capped, "fp64"))
+    res["chaos_cap"] = "5 |1 - i gamma tau/2|^1.5 per problem"
     return res
 
 
@@ -574,10 +584,9 @@ def main():
                              "spectral_db_p90_H15_80": p90})
             plan.close()
             del plan
-            # the same comparison with the prefactor cap |C| <= 1e3 (chaotic
-            # trajectories filtered; the mixed run hands trajectories near the
-            # cap to FP64, so with this cap both runs are mostly FP64)
-            capped = [dict(p, c_max=1e3) for p in probs]
+            # the same comparison with chaotic trajectories cut by a prefactor
+            # cap above free spreading: the FP32 stepping error of the rest
+            capped = [dict(p, c_max=chaos_cap(sf, p)) for p in probs]
             errs_c = []
             pf = sf.Plan(capped, n_traj, seeds, precision="fp64", tuning=tun, h_max=100.0)
             pm = sf.Plan(capped, n_traj, seeds, precision="mixed", tuning=tun, h_max=100.0)
@@ -588,7 +597,8 @@ def main():
                 rel = float(torch.linalg.norm(pm.v_of(i) - pf.v_of(i)) / torch.linalg.norm(pf.v_of(i)))
                 med, p90 = spectral_db(sf, p, pm.v_of(i), pf.v_of(i), 15.0, 80.0)
                 errs_c.append({"theta_deg": round(math.degrees(p["align"]["theta"]), 3),
-                               "rel_l2_vs_fp64": rel, "spectral_db_median_H15_80": med,
+                               "c_max": p["c_max"], "rel_l2_vs_fp64": rel,
+                               "spectral_db_median_H15_80": med,
                                "spectral_db_p90_H15_80": p90})
             pf.close()
             pm.close()
@@ -596,7 +606,7 @@ def main():
             variants["mixed"] = {"workload": wl["name"], "value": live_steps / sec,
                                  "unit": "trajectory-steps/s", "ms_per_step": sec * 1e3,
                                  "tuning": list(tun), "error_vs_fp64": errs,
-                                 "error_vs_fp64_prefactor_cap_1e3": errs_c,
+                                 "error_vs_fp64_chaos_cap": errs_c,
                                  "speedup_vs_fp64": (el / args.steps) / sec,
                                  "roofline": step_roofline(algo_flops, sec)}
         if want("batched"):
