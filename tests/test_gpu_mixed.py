@@ -155,3 +155,21 @@ def test_mixed_error_with_chaos_cap(sf):
         print(f"cap {p['c_max']:.0f} {p['name']} theta={p['align']['theta']:.3f}: "
               f"mixed vs FP64 relative L2 {rel:.3e}", flush=True)
         assert 0 < rel < 5e-3
+
+
+def test_cap_handover_is_the_fp64_trajectory(sf):
+    """With a prefactor cap, a trajectory whose prefactor nears the cap is
+    finished by the FP64 kernel from its birth, so its final state (q, p, M,
+    S, C, sign flips) equals the FP64 run's bit for bit: checked for every
+    live trajectory whose FP64 |C| ends above 0.3 c_max (the hand-over
+    threshold is 0.25 c_max)."""
+    probs = [dict(workloads.n2(0.0), c_max=1e3), dict(workloads.h2_softcore(), c_max=1e3)]
+    n, seeds = [20000, 8000], [1002, 1001]
+    ens, out = both_precisions(sf, probs, n, seeds)
+    fs64, fsm = out["fp64"][1], out["mixed"][1]
+    live = np.nonzero(ens.w.cpu().numpy() > 0)[0]
+    c64 = np.hypot(fs64[43, live], fs64[44, live])
+    near = live[c64 > 0.3 * 1e3]
+    print(f"{near.size} of {live.size} live trajectories end with |C| > 300", flush=True)
+    assert near.size > 0.3 * live.size
+    assert np.array_equal(fsm[:, near], fs64[:, near])
