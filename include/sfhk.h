@@ -205,7 +205,14 @@ sfhk_status sfhk_sample_initial(const sfhk_problem* probs, int32_t n_prob,
  *          sum_{Q<P} (N_Q + 1); the caller zeroes it once, calls may add
  *          further ensembles into it.
  *   final_state: NULL or device double [SFHK_FS_COUNT][ens->capacity].
- *   precision: SFHK_FP64 (everything FP64).
+ *   precision: SFHK_FP64 (everything FP64) or SFHK_MIXED: q, p, the
+ *          potential and its derivatives, the monodromy matrix and det R in
+ *          FP32; S, the root of det R with its branch, the amplitude and the
+ *          sum in FP64.  A trajectory whose FP32 monodromy entry exceeds 1e4,
+ *          or (c_max > 0) whose |C| passes c_max / 4, is re-run in FP64 from
+ *          its birth and deposits from that step on; its final state is then
+ *          the FP64 one.  The mixed result's error against FP64 is measured
+ *          and stated, not bounded by the call.
  * probs/n_prob must be those given to sfhk_sample_initial for `ens`. */
 sfhk_status sfhk_propagate(const sfhk_problem* probs, int32_t n_prob, const sfhk_ensemble* ens,
                            int32_t precision, double* accum, double* final_state,
@@ -278,7 +285,8 @@ size_t sfhk_plan_workspace_bytes(const sfhk_problem* probs, int32_t n_prob,
 
 /* Create a plan and enqueue its set-up (problem tables) on `stream`.
  *   probs, n_per_prob, seeds, first_index: host [n_prob], as sfhk_sample_initial;
- *   precision: SFHK_FP64 or SFHK_MIXED; tuning: NULL for the defaults;
+ *   precision: SFHK_FP64 or SFHK_MIXED (as for sfhk_propagate); tuning: NULL
+ *   for the defaults;
  *   spectra on each problem's harmonic grid w_m = m h_step w_laser, m < n_omega;
  *   ens: device ensemble, capacity >= sum(n_per_prob);
  *   workspace: device, >= sfhk_plan_workspace_bytes;
