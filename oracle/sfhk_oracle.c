@@ -11,6 +11,11 @@
  * RK4, the monodromy derivative is a plain 6x6 matrix product, complex
  * arithmetic is C99 <complex.h>, and the transcendental functions are libm.
  * Where the paper is silent the reading used is stated next to the code.
+ *
+ * Parity unpinned: the overall sign of the amplitude (the minus sign of the
+ * dipole formula of Sec. II.A), to which every computed observable (spectra,
+ * yields, Gabor maps) is blind, and the synthetic GTO tables, which stand in
+ * for the paper's fitted orbitals.
  */
 #include "sfhk_oracle.h"
 

@@ -319,6 +319,27 @@ def test_monodromy_symplectic_with_potential(orc):
         assert abs(np.linalg.det(R)) >= 1 - 1e-6
 
 
+def test_action_variation_is_endpoint_momentum(orc):
+    """Hamilton's principal function: along solutions the first variation of
+    the action is dS = p_T . dq_T - p_0 . dq_0 (the Euler-Lagrange terms
+    vanish).  Two trajectories started at q0 +/- delta e in the full potential
+    and laser, same p0: their action difference equals the endpoint terms to
+    O(delta^2) and the RK4 truncation.  Pins the potential and field terms of
+    the action's integrand (the Volkov pins have V = 0)."""
+    p = workloads.n2(30.0)
+    ics = _live_ics(orc, p, 1002, 2)
+    N = orc.n_steps(p)
+    d = 1e-4
+    for (k0, q0, p0, n, w) in ics:
+        kend = min(N, k0 + 2000)
+        for e in np.eye(3):
+            _, fp = orc.trajectory(p, k0, q0 + d * e, p0, n, k_end=kend, amplitudes=False)
+            _, fm = orc.trajectory(p, k0, q0 - d * e, p0, n, k_end=kend, amplitudes=False)
+            dS = fp[42] - fm[42]
+            want = 0.5 * (fp[3:6] + fm[3:6]) @ (fp[0:3] - fm[0:3]) - p0 @ (2 * d * e)
+            assert abs(dS - want) <= 1e-6 * abs(want) + 1e-12, (k0, e, dS, want)
+
+
 def test_energy_conserved_laser_off(orc):
     """E = 0: H = p^2/2 + V is conserved; drift ~dt^4."""
     base = workloads.laser_off(workloads.n2(25.0))
