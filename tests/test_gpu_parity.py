@@ -195,6 +195,24 @@ def test_dipole_h2_full_workload(sf, orc):
     assert rel_l2(vg, vo) < REL_L2
 
 
+LASER_GRID = [(800.0, 1.0e14, 2.0, 0.0), (1800.0, 4.0e14, 6.0, 2.0), (1200.0, 2.5e14, 3.0, 1.5708),
+              (1000.0, 3.0e14, 5.0, -0.7)]
+
+
+@pytest.mark.parametrize("laser", LASER_GRID)
+def test_dipole_laser_grid_h2(sf, orc, laser):
+    """H2 across the stream's laser ranges (wavelength 800-1800 nm, intensity
+    1-4e14 W/cm^2, 2-6 cycles, CEP): the per-problem field table, step grid
+    and birth sampling against the oracle."""
+    lam, inten, cyc, cep = laser
+    las = dict(workloads.H2_LASER, lambda_nm=lam, intensity_wcm2=inten, n_cycles=cyc, cep=cep)
+    p = workloads.h2_softcore(35.0, laser=las)
+    (vg,), _ = gpu_dipole(sf, [p], [500], [77])
+    vo, _, _ = orc.dipole(p, 77, 0, 500, NTHREADS)
+    assert np.linalg.norm(vo) > 0
+    assert rel_l2(vg, vo) < REL_L2
+
+
 def test_dipole_n2_two_angles(sf, orc):
     probs = [workloads.n2(0.0), workloads.n2(90.0)]
     vg, _ = gpu_dipole(sf, probs, [1500, 1500], [1002, 1002])
