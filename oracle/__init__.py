@@ -12,8 +12,8 @@ import numpy as np
 from . import build as _build
 
 MAX_GTO = 64
-NFINAL = 46
-F_Q, F_P, F_M, F_S, F_CRE, F_CIM, F_FLIPS = 0, 3, 6, 42, 43, 44, 45
+NFINAL = 47
+F_Q, F_P, F_M, F_S, F_CRE, F_CIM, F_FLIPS, F_MMAX = 0, 3, 6, 42, 43, 44, 45, 46
 
 
 class Problem(C.Structure):
@@ -69,6 +69,10 @@ def lib():
         L.orc_run.argtypes = [P, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int32, dp,
                               C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
         L.orc_run.restype = C.c_int
+        L.orc_run_ensemble.argtypes = [P, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int32,
+                                       C.c_double, dp, dp, dp, C.POINTER(C.c_uint64),
+                                       C.POINTER(C.c_uint64)]
+        L.orc_run_ensemble.restype = C.c_int
         L.orc_spectrum.argtypes = [dp, C.c_int32, C.c_double, C.c_double, C.c_double,
                                    dp, C.c_int32, dp, dp, dp]
         L.orc_return_step.argtypes = [P, C.c_int32, dp, dp, dp, C.c_double,
@@ -271,6 +275,28 @@ def run(d, seed, first, n, nthreads=None):
     if rc != 0:
         raise RuntimeError("orc_run failed")
     return acc, ls.value, nl.value
+
+
+def run_ensemble(d, seed, first, n, m_regular=1e4, nthreads=None, finals=True):
+    """orc_run split by each trajectory's largest monodromy entry: dict of
+    accum_all, accum_regular (trajectories with max_k max_ij |M_ij| <= m_regular),
+    finals [n, NFINAL] (zeros for trajectories not propagated; None if
+    finals=False), live_steps, n_live."""
+    P = make_problem(d)
+    N = n_steps(d)
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    acc_all = np.zeros(N + 1)
+    acc_reg = np.zeros(N + 1)
+    fin = np.zeros((n, NFINAL)) if finals else None
+    ls, nl = C.c_uint64(), C.c_uint64()
+    rc = lib().orc_run_ensemble(C.byref(P), int(seed), int(first), int(n), int(nthreads),
+                                float(m_regular), _dp(acc_all), _dp(acc_reg),
+                                _dp(fin) if fin is not None else None, C.byref(ls), C.byref(nl))
+    if rc != 0:
+        raise RuntimeError("orc_run_ensemble failed")
+    return {"accum_all": acc_all, "accum_regular": acc_reg, "finals": fin,
+            "live_steps": ls.value, "n_live": nl.value}
 
 
 def dipole(d, seed, first, n, nthreads=None):

@@ -631,9 +631,12 @@ static int traj_core(const orc_problem* P, int32_t k0, int32_t k_end, const doub
   for (int a = 0; a < 6; ++a) y[6 + 6 * a + a] = 1.0;
   double complex C = 1.0, Dprev = 1.0;
   double flips = 0.0;
+  double mmax = 0.0; /* largest |M_ij| over the steps reached */
   double t0 = orc_time(P, k0);
   double p0q0 = p0[0] * q0[0] + p0[1] * q0[1] + p0[2] * q0[2];
   for (int32_t k = k0;; ++k) {
+    for (int i = 0; i < 36; ++i)
+      if (fabs(y[6 + i]) > mmax) mmax = fabs(y[6 + i]);
     double complex D = hk_det(y + 6, P->gamma);
     double complex c = csqrt(D);
     if (creal(c * conj(C)) < 0.0) c = -c;
@@ -658,6 +661,7 @@ static int traj_core(const orc_problem* P, int32_t k0, int32_t k_end, const doub
     final_state[ORC_F_CRE] = creal(C);
     final_state[ORC_F_CIM] = cimag(C);
     final_state[ORC_F_FLIPS] = flips;
+    final_state[ORC_F_MMAX] = mmax;
   }
   return 0;
 }
@@ -773,6 +777,109 @@ int orc_run(const orc_problem* P, uint64_t seed, uint64_t first, uint64_t n, int
   free(jobs);
   free(th);
   return 0;
+}
+
+/* The same sum split by each trajectory's largest monodromy entry.  Near a
+ * nucleus a trajectory can grow its monodromy matrix by many orders of
+ * magnitude; rounding differences between two correct FP64 evaluations grow
+ * with it, so comparisons across implementations treat these trajectories
+ * apart.  A trajectory's amplitudes go into a buffer of its own first and
+ * are then added to accum_all, and to accum_regular if its largest entry is
+ * <= m_regular; per thread in index order, threads in order (the same
+ * additions as orc_run, so accum_all equals orc_run's accum). */
+typedef struct {
+  const orc_problem* P;
+  uint64_t seed, first, n;
+  double m_regular;
+  double *all, *regular, *finals;
+  uint64_t live_steps, n_live;
+} orc_split_job;
+
+static void* run_split_range(void* arg) {
+  orc_split_job* J = (orc_split_job*)arg;
+  double E0;
+  int32_t N;
+  orc_laser(J->P, NULL, &E0, NULL, &N);
+  double* buf = (double*)calloc((size_t)N + 1, sizeof(double));
+  double fin[ORC_NFINAL];
+  if (!buf) return (void*)1;
+  for (uint64_t i = 0; i < J->n; ++i) {
+    int32_t k0;
+    double q0[3], p0[3], nax[3], w, dph;
+    sample_one(J->P, J->seed, J->first + i, N, E0, &k0, q0, p0, nax, &w, &dph);
+    double* row = J->finals ? J->finals + i * (uint64_t)ORC_NFINAL : NULL;
+    if (w == 0.0) {
+      if (row) memset(row, 0, sizeof(double) * ORC_NFINAL);
+      continue;
+    }
+    for (int32_t k = k0; k <= N; ++k) buf[k] = 0.0;
+    traj_core(J->P, k0, N, q0, p0, nax, w, dph, buf, NULL, NULL, NULL, NULL, fin);
+    const int regular = fin[ORC_F_MMAX] <= J->m_regular;
+    for (int32_t k = k0; k <= N; ++k) {
+      J->all[k] += buf[k];
+      if (regular) J->regular[k] += buf[k];
+    }
+    if (row) memcpy(row, fin, sizeof fin);
+    J->live_steps += (uint64_t)(N - k0);
+    J->n_live += 1;
+  }
+  free(buf);
+  return NULL;
+}
+
+int orc_run_ensemble(const orc_problem* P, uint64_t seed, uint64_t first, uint64_t n,
+                     int32_t nthreads, double m_regular, double* accum_all,
+                     double* accum_regular, double* finals, uint64_t* live_steps,
+                     uint64_t* n_live) {
+  int32_t N;
+  orc_laser(P, NULL, NULL, NULL, &N);
+  if (!accum_all || !accum_regular) return -1;
+  if (nthreads < 1) nthreads = 1;
+  if ((uint64_t)nthreads > n && n > 0) nthreads = (int32_t)n;
+  orc_split_job* jobs = (orc_split_job*)calloc((size_t)nthreads, sizeof(orc_split_job));
+  pthread_t* th = (pthread_t*)calloc((size_t)nthreads, sizeof(pthread_t));
+  int fail = !jobs || !th;
+  uint64_t base = 0;
+  for (int32_t t = 0; !fail && t < nthreads; ++t) {
+    uint64_t cnt = n / (uint64_t)nthreads + ((uint64_t)t < n % (uint64_t)nthreads ? 1 : 0);
+    jobs[t].P = P;
+    jobs[t].seed = seed;
+    jobs[t].first = first + base;
+    jobs[t].n = cnt;
+    jobs[t].m_regular = m_regular;
+    jobs[t].all = (double*)calloc((size_t)N + 1, sizeof(double));
+    jobs[t].regular = (double*)calloc((size_t)N + 1, sizeof(double));
+    jobs[t].finals = finals ? finals + base * (uint64_t)ORC_NFINAL : NULL;
+    if (!jobs[t].all || !jobs[t].regular) fail = 1;
+    base += cnt;
+  }
+  if (!fail) {
+    for (int32_t t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, run_split_range, &jobs[t]);
+    for (int32_t t = 0; t < nthreads; ++t) {
+      void* r = NULL;
+      pthread_join(th[t], &r);
+      if (r) fail = 1;
+    }
+  }
+  uint64_t ls = 0, nl = 0;
+  for (int32_t k = 0; k <= N; ++k) accum_all[k] = accum_regular[k] = 0.0;
+  for (int32_t t = 0; jobs && t < nthreads; ++t) {
+    if (!fail) {
+      for (int32_t k = 0; k <= N; ++k) {
+        accum_all[k] += jobs[t].all[k];
+        accum_regular[k] += jobs[t].regular[k];
+      }
+      ls += jobs[t].live_steps;
+      nl += jobs[t].n_live;
+    }
+    free(jobs[t].all);
+    free(jobs[t].regular);
+  }
+  if (live_steps) *live_steps = ls;
+  if (n_live) *n_live = nl;
+  free(jobs);
+  free(th);
+  return fail ? -1 : 0;
 }
 
 /* --------------------------------------------------------------- spectrum */

@@ -29,7 +29,8 @@ enum {
   ORC_F_CRE = 43,   /* HK prefactor C, real part                            */
   ORC_F_CIM = 44,   /* HK prefactor C, imaginary part                       */
   ORC_F_FLIPS = 45, /* steps where arg(D_k / D_{k-1}) exceeded pi/2        */
-  ORC_NFINAL = 46
+  ORC_F_MMAX = 46,  /* largest |M_ij| over the grid steps reached (>= 1)   */
+  ORC_NFINAL = 47
 };
 
 enum { ORC_ALIGN_FIXED = 0, ORC_ALIGN_COS2M = 1 };
@@ -105,6 +106,17 @@ int orc_trajectory(const orc_problem* P, int32_t k0, int32_t k_end, const double
  * ones, accum[k] = sum_j Re a_jk (length N+1).  Returns 0 or -1. */
 int orc_run(const orc_problem* P, uint64_t seed, uint64_t first, uint64_t n, int32_t nthreads,
             double* accum, uint64_t* live_steps, uint64_t* n_live);
+/* orc_run with the sum split by how strongly each trajectory amplifies
+ * perturbations: accum_all[k] = sum_j Re a_jk over every live trajectory,
+ * accum_regular[k] the same over those whose largest monodromy entry along
+ * the trajectory, max_k max_ij |M_ij(t_k)|, stays <= m_regular.  finals
+ * (nullable) receives ORC_NFINAL doubles per trajectory index (row i for
+ * trajectory first + i; zeros for a trajectory that is not propagated).
+ * Returns 0 or -1. */
+int orc_run_ensemble(const orc_problem* P, uint64_t seed, uint64_t first, uint64_t n,
+                     int32_t nthreads, double m_regular, double* accum_all,
+                     double* accum_regular, double* finals, uint64_t* live_steps,
+                     uint64_t* n_live);
 /* windowed Fourier transform of v on the grid t_first + k dt, k < n_t */
 void orc_spectrum(const double* v, int32_t n_t, double t_first, double dt, double tau_H,
                   const double* omega, int32_t n_omega, double* V_re, double* V_im,

@@ -442,6 +442,54 @@ def test_linearity_of_ensemble_sum(orc):
     assert ls_a + ls_b == ls_c and nl_a + nl_b == nl_c
 
 
+def test_free_monodromy_max_entry(orc):
+    """V = 0: the largest monodromy entry along a trajectory is max(1, t_N - t0)
+    (M = [[I, (t - t0) I], [0, I]]), for every trajectory of a run."""
+    p = workloads.free_problem(workloads.h2_softcore(0.0))
+    N = orc.n_steps(p)
+    r = orc.run_ensemble(p, 1001, 0, 300, m_regular=1e4, nthreads=4)
+    s = orc.sample(p, 1001, 0, 300)
+    live = s["w"] > 0
+    assert live.sum() > 50
+    tN = orc.time(p, N)
+    want = np.array([max(1.0, tN - orc.time(p, int(k))) for k in s["k0"]])
+    got = r["finals"][:, orc.F_MMAX]
+    assert np.all(np.abs(got[live] - want[live]) <= 1e-11 * want[live])
+    assert np.all(r["finals"][~live] == 0.0)
+
+
+def test_split_ensemble_sum(orc):
+    """The split run on an N2 sample with chaotic trajectories: the full sum
+    equals the plain run; the regular part plus the chaotic trajectories'
+    amplitudes, each propagated alone, gives the full sum; the running maximum
+    bounds the final monodromy; thresholds at infinity and below 1 select
+    everything and nothing (M starts at the identity)."""
+    p = workloads.n2(0.0)
+    n, seed, nt = 2000, 1002, 8
+    r = orc.run_ensemble(p, seed, 0, n, m_regular=1e4, nthreads=nt)
+    acc, ls, nl = orc.run(p, seed, 0, n, nthreads=nt)
+    assert np.array_equal(r["accum_all"], acc)
+    assert (r["live_steps"], r["n_live"]) == (ls, nl)
+    s = orc.sample(p, seed, 0, n)
+    fin = r["finals"]
+    live = s["w"] > 0
+    mmax = fin[:, orc.F_MMAX]
+    chaotic = np.nonzero(live & (mmax > 1e4))[0]
+    assert 0 < len(chaotic) < 0.05 * live.sum()
+    assert np.all(mmax[live] >= np.max(np.abs(fin[live, 6:42]), axis=1))
+    assert np.all(mmax[live] >= 1.0)
+    extra = np.zeros_like(acc)
+    for i in chaotic:
+        a, _ = orc.trajectory(p, int(s["k0"][i]), s["q0"][i], s["p0"][i], s["nax"][i], w=s["w"][i])
+        extra += a.real
+    scale = np.max(np.abs(acc))
+    assert np.max(np.abs(r["accum_regular"] + extra - acc)) <= 1e-12 * scale
+    r_all = orc.run_ensemble(p, seed, 0, 300, m_regular=np.inf, nthreads=nt, finals=False)
+    assert np.array_equal(r_all["accum_regular"], r_all["accum_all"])
+    r_none = orc.run_ensemble(p, seed, 0, 300, m_regular=0.5, nthreads=nt, finals=False)
+    assert np.all(r_none["accum_regular"] == 0.0) and np.any(r_none["accum_all"] != 0.0)
+
+
 # ---------------------------------------------------------------- spectrum
 def test_spectrum_equals_fft(orc):
     """On the FFT grid the windowed transform is a library FFT."""
