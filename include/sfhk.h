@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define SFHK_ABI_VERSION 2
+#define SFHK_ABI_VERSION 3
 #define SFHK_MAX_GTO 64
 #define SFHK_MAX_PROBLEMS 65535
 
@@ -163,8 +163,12 @@ enum {
   SFHK_FS_S = 42,     /* continuum action S                                      */
   SFHK_FS_CRE = 43,   /* HK prefactor C (real)                                   */
   SFHK_FS_CIM = 44,   /* HK prefactor C (imaginary)                              */
-  SFHK_FS_FLIPS = 45, /* steps with Re(D_k conj(D_{k-1})) < 0                    */
-  SFHK_FS_COUNT = 46
+  SFHK_FS_FLIPS = 45, /* steps at which arg(D_k / D_{k-1}) left (-pi/2, pi/2]      */
+  SFHK_FS_MMAX = 46,  /* largest |M_ij| over the grid steps reached (>= 1): how far
+                         the trajectory amplifies perturbations                  */
+  SFHK_FS_NEAR = 47,  /* steps at which the kernel evaluated the recombination sum
+                         (a shell of psi_0 passed its far-field cut)             */
+  SFHK_FS_COUNT = 48
 };
 
 /* SFHK_ABI_VERSION of the library. */
@@ -179,8 +183,18 @@ sfhk_status sfhk_problem_steps(const sfhk_problem* p, int32_t* n_steps, double* 
                                double* tau);
 
 /* Host only.  Bytes of device workspace that sfhk_sample_initial and
- * sfhk_propagate need for these problems and `capacity` slots. */
+ * sfhk_propagate (either precision) need for these problems and `capacity`
+ * slots.  0 for invalid problems. */
 size_t sfhk_workspace_bytes(const sfhk_problem* probs, int32_t n_prob, uint64_t capacity);
+
+/* Host only.  Device bytes of the whole path for one problem of n_traj
+ * trajectories at `precision` (Sec. II.A-B: the sampled ensemble and its
+ * packing, the propagation's workspace, the dipole accumulator and v): the
+ * sum of the 256-byte aligned arrays sfhk_ensemble (capacity n_traj, one
+ * problem), a workspace of sfhk_propagate at this precision (which also
+ * serves sfhk_sample_initial) and accum and v of N + 1 doubles each.  The
+ * admission size of a request.  0 for an invalid problem or precision. */
+size_t sfhk_footprint_bytes(const sfhk_problem* p, uint64_t n_traj, int32_t precision);
 
 /* Sample the ensemble (Sec. II.A tunnel exit; Sec. II.B joint alignment):
  * for problem P, trajectories first_index[P] .. + n_per_prob[P] - 1 drawn
@@ -204,18 +218,30 @@ sfhk_status sfhk_sample_initial(const sfhk_problem* probs, int32_t n_prob,
  *   accum: device double [sum_P (N_P + 1)], problem P at offset
  *          sum_{Q<P} (N_Q + 1); the caller zeroes it once, calls may add
  *          further ensembles into it.
- *   final_state: NULL or device double [SFHK_FS_COUNT][ens->capacity].
+ *   final_state: NULL or device double [SFHK_FS_COUNT][ens->capacity]: the
+ *          record (SFHK_FS_*) of every live slot at the last step it reached.
+ *   snapshots: NULL or device double [n_snap][SFHK_FS_COUNT][ens->capacity]:
+ *          snapshot s (0 <= s < n_snap) is the same record at grid step
+ *          k = s snap_every, written for the live slots with k0 <= k <= the
+ *          last step they reach (entries of other slots and steps are left
+ *          as they were; the caller fills them if it needs to tell).
+ *          n_snap >= 1 and snap_every >= 1 when snapshots is non-null.
+ *          Asking for either record runs the one-wavefront-per-pack kernel
+ *          that keeps them (same arithmetic as without).
  *   precision: SFHK_FP64 (everything FP64) or SFHK_MIXED: q, p, the
  *          potential and its derivatives, the monodromy matrix and det R in
  *          FP32; S, the root of det R with its branch, the amplitude and the
  *          sum in FP64.  A trajectory whose FP32 monodromy entry exceeds 1e4,
  *          or (c_max > 0) whose |C| passes c_max / 4, is re-run in FP64 from
- *          its birth and deposits from that step on; its final state is then
- *          the FP64 one.  The mixed result's error against FP64 is measured
+ *          its birth and deposits from that step on; its records are then
+ *          the FP64 ones.  The mixed result's error against FP64 is measured
  *          and stated, not bounded by the call.
- * probs/n_prob must be those given to sfhk_sample_initial for `ens`. */
+ * probs/n_prob must be those given to sfhk_sample_initial for `ens`;
+ * workspace: device, >= sfhk_workspace_bytes (or the precision's share
+ * counted by sfhk_footprint_bytes for a single problem). */
 sfhk_status sfhk_propagate(const sfhk_problem* probs, int32_t n_prob, const sfhk_ensemble* ens,
                            int32_t precision, double* accum, double* final_state,
+                           double* snapshots, int32_t n_snap, int32_t snap_every,
                            void* workspace, size_t workspace_bytes, void* stream);
 
 /* Dipole velocity (Sec. II.A, Eq. 4-6): v_k = (2 / n_sampled[P]) accum_k for
@@ -311,7 +337,14 @@ sfhk_status sfhk_plan_capture(sfhk_plan* plan, void* stream);
 /* Launch the recorded graph on `stream` (SFHK_E_INVALID if none). */
 sfhk_status sfhk_plan_replay(sfhk_plan* plan, void* stream);
 
-/* Release the plan and its graph (host resources only). */
+/* Measurement: durations in ms of the trajectory kernel (ms[0]) and, for
+ * SFHK_MIXED, of the FP64 re-run of the trajectories it handed over (ms[1];
+ * 0 for SFHK_FP64) in the last sfhk_plan_run of this plan, from HIP events
+ * the run records around them on its stream.  Recordings and replays record
+ * none.  The run must have completed; SFHK_E_INVALID if the plan never ran. */
+sfhk_status sfhk_plan_kernel_ms(sfhk_plan* plan, float ms[2]);
+
+/* Release the plan, its graph and its events (host resources only). */
 void sfhk_plan_destroy(sfhk_plan* plan);
 
 /* ---------------------------------------------------------------- serving

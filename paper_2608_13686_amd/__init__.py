@@ -11,11 +11,12 @@ import math
 import torch
 
 from . import _abi
-from ._abi import FS_COUNT, FS_CIM, FS_CRE, FS_FLIPS, FS_M, FS_P, FS_Q, FS_S, SfhkError
+from ._abi import (FS_COUNT, FS_CIM, FS_CRE, FS_FLIPS, FS_M, FS_MMAX, FS_NEAR, FS_P, FS_Q, FS_S,
+                   SfhkError)
 
-__all__ = ["problem_steps", "workspace_bytes", "Ensemble", "sample_initial", "propagate",
-           "dipole", "spectrum", "run", "SfhkError", "harmonic_grid", "abi_version", "Plan",
-           "accum_layout", "gabor", "gabor_width", "return_steps"]
+__all__ = ["problem_steps", "workspace_bytes", "footprint_bytes", "Ensemble", "sample_initial",
+           "propagate", "dipole", "spectrum", "run", "SfhkError", "harmonic_grid", "abi_version",
+           "Plan", "accum_layout", "gabor", "gabor_width", "return_steps"]
 
 PRECISION = {"fp64": _abi.FP64, "mixed": _abi.MIXED}
 
@@ -60,6 +61,15 @@ def workspace_bytes(probs, capacity):
     nb = _abi.lib().sfhk_workspace_bytes(arr, len(probs), int(capacity))
     if nb == 0:
         raise SfhkError(1, "sfhk_workspace_bytes")
+    return nb
+
+
+def footprint_bytes(prob, n_traj, precision="fp64"):
+    """Device bytes of the whole path for one problem (sfhk_footprint_bytes)."""
+    arr = _abi.make_problems([prob])
+    nb = _abi.lib().sfhk_footprint_bytes(arr, int(n_traj), PRECISION[precision])
+    if nb == 0:
+        raise SfhkError(1, "sfhk_footprint_bytes")
     return nb
 
 
@@ -128,9 +138,12 @@ def sample_initial(probs, n_per_prob, seeds, first_index=None, ens=None, workspa
 
 @_on_stream
 def propagate(probs, ens, precision="fp64", accum=None, final_state=False, workspace=None,
-              stream=None):
+              snapshots=None, stream=None):
     """Propagate the ensemble and add sum_j Re a_jk into accum (created zeroed
-    if None).  Returns (accum, final_state or None)."""
+    if None).  snapshots=(n_snap, snap_every) also records the state at the
+    steps s snap_every, s < n_snap (a [n_snap, FS_COUNT, capacity] tensor
+    filled with NaN where no record is written).  Returns (accum, final_state
+    or None), or (accum, final_state, snapshots) when snapshots are asked for."""
     n_prob = len(probs)
     arr = _abi.make_problems(probs)
     dev = ens.k0.device
@@ -145,11 +158,19 @@ def propagate(probs, ens, precision="fp64", accum=None, final_state=False, works
     fs = None
     if final_state:
         fs = torch.zeros((FS_COUNT, max(ens.capacity, 1)), dtype=torch.float64, device=dev)
+    snap, n_snap, every = None, 0, 1
+    if snapshots is not None:
+        n_snap, every = int(snapshots[0]), int(snapshots[1])
+        snap = torch.full((max(n_snap, 1), FS_COUNT, max(ens.capacity, 1)), float("nan"),
+                          dtype=torch.float64, device=dev)
     es = ens.struct()
     _abi.check(_abi.lib().sfhk_propagate(
         arr, n_prob, C.byref(es), PRECISION[precision], C.c_void_p(accum.data_ptr()),
-        C.c_void_p(fs.data_ptr() if fs is not None else 0), C.c_void_p(workspace.data_ptr()),
-        workspace.numel(), _stream(stream)), "sfhk_propagate")
+        C.c_void_p(fs.data_ptr() if fs is not None else 0),
+        C.c_void_p(snap.data_ptr() if snap is not None else 0), n_snap, every,
+        C.c_void_p(workspace.data_ptr()), workspace.numel(), _stream(stream)), "sfhk_propagate")
+    if snapshots is not None:
+        return accum, fs, snap
     return accum, fs
 
 
@@ -266,6 +287,7 @@ class Plan:
     def __init__(self, probs, n_traj, seeds, precision="fp64", tuning=None, h_max=40.0,
                  h_step=0.05, first_index=None, device="cuda", stream=None):
         self.probs = list(probs)
+        self.precision = precision
         n_prob = len(self.probs)
         self.n_traj = [int(n) for n in n_traj]
         self.first_index = [0] * n_prob if first_index is None else list(first_index)
@@ -327,6 +349,13 @@ class Plan:
 
     def replay(self, stream=None):
         _abi.check(_abi.lib().sfhk_plan_replay(self._h, self._on(stream)), "sfhk_plan_replay")
+
+    def kernel_ms(self):
+        """(trajectory kernel, FP64 re-run) durations in ms of the last run()
+        (HIP events on its stream; 0 for the re-run of an FP64 plan)."""
+        ms = (C.c_float * 2)()
+        _abi.check(_abi.lib().sfhk_plan_kernel_ms(self._h, ms), "sfhk_plan_kernel_ms")
+        return ms[0], ms[1]
 
     @property
     def V(self):

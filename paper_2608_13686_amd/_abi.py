@@ -7,15 +7,17 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsfhk.so"
 MAX_GTO = 64
 FP64, MIXED = 0, 1
 ALIGN_FIXED, ALIGN_COS2M = 0, 1
-FS_Q, FS_P, FS_M, FS_S, FS_CRE, FS_CIM, FS_FLIPS, FS_COUNT = 0, 3, 6, 42, 43, 44, 45, 46
+FS_Q, FS_P, FS_M, FS_S, FS_CRE, FS_CIM, FS_FLIPS = 0, 3, 6, 42, 43, 44, 45
+FS_MMAX, FS_NEAR, FS_COUNT = 46, 47, 48
 
 STATUS = {0: "SFHK_OK", 1: "SFHK_E_INVALID", 2: "SFHK_E_NOMEM", 3: "SFHK_E_DEVICE",
           4: "SFHK_E_BUSY", 5: "SFHK_E_UNSUPPORTED"}
 
 EXPORTS = ["sfhk_abi_version", "sfhk_last_error", "sfhk_problem_steps", "sfhk_workspace_bytes",
+           "sfhk_footprint_bytes",
            "sfhk_sample_initial", "sfhk_propagate", "sfhk_dipole", "sfhk_spectrum",
            "sfhk_plan_workspace_bytes", "sfhk_plan_create", "sfhk_plan_run", "sfhk_plan_capture",
-           "sfhk_plan_replay", "sfhk_plan_destroy", "sfhk_request_bytes", "sfhk_request_layout",
+           "sfhk_plan_replay", "sfhk_plan_destroy", "sfhk_plan_kernel_ms", "sfhk_request_bytes", "sfhk_request_layout",
            "sfhk_request_table_bytes", "sfhk_request_init", "sfhk_serve_window",
            "sfhk_request_finalize", "sfhk_gabor", "sfhk_return_steps"]
 
@@ -91,8 +93,11 @@ def lib():
         L.sfhk_sample_initial.argtypes = [P, C.c_int32, u64p, u64p, u64p, C.POINTER(Ensemble),
                                           C.c_void_p, C.c_size_t, C.c_void_p]
         L.sfhk_sample_initial.restype = C.c_int
+        L.sfhk_footprint_bytes.argtypes = [P, C.c_uint64, C.c_int32]
+        L.sfhk_footprint_bytes.restype = C.c_size_t
         L.sfhk_propagate.argtypes = [P, C.c_int32, C.POINTER(Ensemble), C.c_int32, C.c_void_p,
-                                     C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+                                     C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                     C.c_void_p, C.c_size_t, C.c_void_p]
         L.sfhk_propagate.restype = C.c_int
         L.sfhk_dipole.argtypes = [P, C.c_int32, C.c_void_p, u64p, C.c_void_p, C.c_void_p]
         L.sfhk_dipole.restype = C.c_int
@@ -111,6 +116,8 @@ def lib():
         for f in ("sfhk_plan_run", "sfhk_plan_capture", "sfhk_plan_replay"):
             getattr(L, f).argtypes = [C.c_void_p, C.c_void_p]
             getattr(L, f).restype = C.c_int
+        L.sfhk_plan_kernel_ms.argtypes = [C.c_void_p, C.POINTER(C.c_float)]
+        L.sfhk_plan_kernel_ms.restype = C.c_int
         L.sfhk_plan_destroy.argtypes = [C.c_void_p]
         L.sfhk_plan_destroy.restype = None
         L.sfhk_request_bytes.argtypes = [P, C.c_uint64, C.c_int32]

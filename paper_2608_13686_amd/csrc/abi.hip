@@ -209,9 +209,12 @@ Desc make_desc(const sfhk_problem& p) {
   return d;
 }
 
-// Descriptors with field/accum offsets; returns the layout.
+// Descriptors with field/accum offsets; returns the layout.  The mixed
+// precision's hand-over arrays (redo, order2, runs2) are laid out only for
+// SFHK_MIXED (the default covers both precisions).
 Layout build_layout(const sfhk_problem* probs, int32_t n_prob, uint64_t n_slots,
-                    std::vector<Desc>* descs, int64_t* max_steps, bool with_queue = false) {
+                    std::vector<Desc>* descs, int64_t* max_steps, bool with_queue = false,
+                    int precision = SFHK_MIXED) {
   Layout L;
   uint64_t fo = 0, ao = 0;
   int64_t mx = 0;
@@ -243,12 +246,14 @@ Layout build_layout(const sfhk_problem* probs, int32_t n_prob, uint64_t n_slots,
   off = align256(off + sizeof(uint32_t) * (size_t)(L.n_bins + 1));
   L.off_cursor = off;
   off = align256(off + sizeof(uint32_t) * (size_t)(L.n_bins + 1));
-  L.off_redo = off;
-  off = align256(off + sizeof(int32_t) * (size_t)n_slots);
-  L.off_order2 = off;
-  off = align256(off + sizeof(uint32_t) * (size_t)n_slots);
-  L.off_runs2 = off;
-  off = align256(off + sizeof(uint32_t) * (3 * (size_t)n_prob + 1));
+  if (precision == SFHK_MIXED) {
+    L.off_redo = off;
+    off = align256(off + sizeof(int32_t) * (size_t)n_slots);
+    L.off_order2 = off;
+    off = align256(off + sizeof(uint32_t) * (size_t)n_slots);
+    L.off_runs2 = off;
+    off = align256(off + sizeof(uint32_t) * (3 * (size_t)n_prob + 1));
+  }
   if (with_queue) {
     L.max_packs = (uint32_t)((n_slots + kWave - 1) / kWave + (uint64_t)n_prob);
     L.n_len = (uint32_t)(mx + 1);
@@ -278,9 +283,9 @@ Workspace carve(void* base, const Layout& L) {
   w.field = reinterpret_cast<double*>(b + L.off_field);
   w.hist = reinterpret_cast<uint32_t*>(b + L.off_hist);
   w.cursor = reinterpret_cast<uint32_t*>(b + L.off_cursor);
-  w.redo = reinterpret_cast<int32_t*>(b + L.off_redo);
-  w.order2 = reinterpret_cast<uint32_t*>(b + L.off_order2);
-  w.runs2 = reinterpret_cast<uint32_t*>(b + L.off_runs2);
+  w.redo = L.off_redo ? reinterpret_cast<int32_t*>(b + L.off_redo) : nullptr;
+  w.order2 = L.off_order2 ? reinterpret_cast<uint32_t*>(b + L.off_order2) : nullptr;
+  w.runs2 = L.off_runs2 ? reinterpret_cast<uint32_t*>(b + L.off_runs2) : nullptr;
   w.bytes = L.bytes;
   return w;
 }
@@ -337,6 +342,83 @@ sfhk_status stage_problems(const std::vector<Desc>& descs, const Workspace& ws,
   return SFHK_OK;
 }
 
+// Argument checks, descriptors and workspace layout of a propagation.
+sfhk_status propagate_prepare(const sfhk_problem* probs, int32_t n_prob, const sfhk_ensemble* ens,
+                              int32_t precision, double* accum, double* snapshots,
+                              int32_t n_snap, int32_t snap_every, std::vector<Desc>& descs,
+                              int64_t& max_steps, Layout& L) {
+  sfhk_status st = check_problems(probs, n_prob);
+  if (st != SFHK_OK) return st;
+  if ((st = check_ensemble(ens)) != SFHK_OK) return st;
+  if (precision != SFHK_FP64 && precision != SFHK_MIXED)
+    return fail(SFHK_E_INVALID, "unknown precision %d", precision);
+  if (!accum) return fail(SFHK_E_INVALID, "accum is null");
+  if (snapshots && (n_snap < 1 || snap_every < 1))
+    return fail(SFHK_E_INVALID, "snapshots need n_snap >= 1 and snap_every >= 1");
+  L = build_layout(probs, n_prob, ens->capacity, &descs, &max_steps, false, precision);
+  return SFHK_OK;
+}
+
+Records make_records(const sfhk_ensemble* ens, double* final_state, double* snapshots,
+                     int32_t n_snap, int32_t snap_every) {
+  Records rec;
+  rec.final_state = final_state;
+  rec.snap = snapshots;
+  rec.n_snap = snapshots ? n_snap : 0;
+  rec.snap_every = snapshots ? snap_every : 1;
+  rec.capacity = ens->capacity;
+  return rec;
+}
+
+// Propagation of a sampled ensemble whose problems are staged in ws: FP64,
+// or FP32 stepping for every trajectory with the ones whose monodromy matrix
+// grows past the FP32 bound handed over, at that step, to an FP64 re-run from
+// their birth (sorted into packs of their own).
+sfhk_status propagate_enqueue(int n_prob, const sfhk_ensemble* ens, int precision, double* accum,
+                              const Records& rec, const Workspace& ws, const Layout& L,
+                              hipStream_t s) {
+  // one wavefront per 64-lane pack; packs never straddle problems
+  const uint64_t max_packs = (ens->capacity + kWave - 1) / kWave + (uint64_t)n_prob;
+  if (max_packs > 0x7fffffffull) return fail(SFHK_E_UNSUPPORTED, "ensemble too large");
+  EnsPtrs ep = ens_ptrs(ens);
+  hipError_t e;
+  if (precision == SFHK_FP64) {
+    e = launch_propagate_f64(ws.descs, n_prob, ws.field, ep, nullptr, (uint32_t)max_packs, accum,
+                             rec, s, LaunchCfg{});
+  } else {
+    e = launch_fill_i32(ws.redo, -1, ens->capacity, s);
+    if (e == hipSuccess)
+      e = launch_propagate_mixed(ws.descs, n_prob, ws.field, ep, ws.redo, (uint32_t)max_packs,
+                                 accum, rec, s, LaunchCfg{});
+    if (e == hipSuccess) e = launch_fill_u32(ws.hist, 0u, L.n_bins + 1, s);
+    if (e == hipSuccess) e = launch_count(ws.descs, ens->capacity, ep, ws.redo, ws.hist, s);
+    PackOut po{ws.order2, ws.runs2, ws.runs2 + n_prob, ws.runs2 + 2 * n_prob};
+    if (e == hipSuccess)
+      e = launch_sort(ws.descs, n_prob, ens->capacity, L.n_bins, ws.hist, ws.cursor, ep, ws.redo,
+                      po, s);
+    if (e == hipSuccess) {
+      EnsPtrs e2 = ep;
+      e2.order = po.order;
+      e2.live_start = po.live_start;
+      e2.live_count = po.live_count;
+      e2.pack_start = po.pack_start;
+      e = launch_propagate_f64(ws.descs, n_prob, ws.field, e2, ws.redo, (uint32_t)max_packs,
+                               accum, rec, s, LaunchCfg{});
+    }
+  }
+  if (e != hipSuccess) return hip_fail(e, "propagate");
+  return ok();
+}
+
+// Bytes of the ensemble arrays of sfhk_ensemble for `capacity` slots and
+// n_prob problems, each array 256-byte aligned.
+size_t ensemble_bytes(uint64_t capacity, int n_prob) {
+  const size_t c = (size_t)std::max<uint64_t>(capacity, 1);
+  return 2 * align256(sizeof(int32_t) * c) + 11 * align256(sizeof(double) * c) +
+         align256(sizeof(uint32_t) * c) + 2 * align256(sizeof(uint32_t) * (size_t)n_prob) +
+         align256(sizeof(uint32_t) * ((size_t)n_prob + 1));
+}
+
 }  // namespace
 
 // entry points of this file used by the serving ABI (serve_abi.hip)
@@ -373,6 +455,25 @@ size_t sfhk_workspace_bytes(const sfhk_problem* probs, int32_t n_prob, uint64_t 
   return build_layout(probs, n_prob, capacity, nullptr, nullptr).bytes;
 }
 
+size_t sfhk_footprint_bytes(const sfhk_problem* p, uint64_t n_traj, int32_t precision) {
+  if (check_problems(p, 1) != SFHK_OK) return 0;
+  if (precision != SFHK_FP64 && precision != SFHK_MIXED) {
+    fail(SFHK_E_INVALID, "unknown precision %d", precision);
+    return 0;
+  }
+  if (n_traj >= (uint64_t(1) << 32)) {
+    fail(SFHK_E_INVALID, "n_traj must be < 2^32");
+    return 0;
+  }
+  double omega, E0, tau;
+  int64_t N;
+  laser_consts(*p, omega, E0, tau, N);
+  g_err.clear();
+  return ensemble_bytes(n_traj, 1) +
+         build_layout(p, 1, n_traj, nullptr, nullptr, false, precision).bytes +
+         2 * align256(sizeof(double) * (size_t)(N + 1));
+}
+
 sfhk_status sfhk_sample_initial(const sfhk_problem* probs, int32_t n_prob,
                                 const uint64_t* n_per_prob, const uint64_t* seeds,
                                 const uint64_t* first_index, const sfhk_ensemble* ens,
@@ -394,7 +495,8 @@ sfhk_status sfhk_sample_initial(const sfhk_problem* probs, int32_t n_prob,
                 (unsigned long long)n_slots, (unsigned long long)ens->capacity);
   std::vector<Desc> descs;
   int64_t max_steps = 0;
-  Layout L = build_layout(probs, n_prob, n_slots, &descs, &max_steps);
+  // sampling uses no hand-over arrays: the FP64 layout (a prefix of both)
+  Layout L = build_layout(probs, n_prob, n_slots, &descs, &max_steps, false, SFHK_FP64);
   if (L.n_bins + 1 >= (uint64_t(1) << 31))
     return fail(SFHK_E_UNSUPPORTED, "total step count of the problems too large");
   if (!workspace) return fail(SFHK_E_INVALID, "workspace is null");
@@ -422,16 +524,14 @@ sfhk_status sfhk_sample_initial(const sfhk_problem* probs, int32_t n_prob,
 
 sfhk_status sfhk_propagate(const sfhk_problem* probs, int32_t n_prob, const sfhk_ensemble* ens,
                            int32_t precision, double* accum, double* final_state,
+                           double* snapshots, int32_t n_snap, int32_t snap_every,
                            void* workspace, size_t workspace_bytes, void* stream) {
-  sfhk_status st = check_problems(probs, n_prob);
-  if (st != SFHK_OK) return st;
-  if ((st = check_ensemble(ens)) != SFHK_OK) return st;
-  if (precision != SFHK_FP64 && precision != SFHK_MIXED)
-    return fail(SFHK_E_INVALID, "unknown precision %d", precision);
-  if (!accum) return fail(SFHK_E_INVALID, "accum is null");
   std::vector<Desc> descs;
   int64_t max_steps = 0;
-  Layout L = build_layout(probs, n_prob, ens->capacity, &descs, &max_steps);
+  Layout L;
+  sfhk_status st = propagate_prepare(probs, n_prob, ens, precision, accum, snapshots, n_snap,
+                                     snap_every, descs, max_steps, L);
+  if (st != SFHK_OK) return st;
   if (!workspace) return fail(SFHK_E_INVALID, "workspace is null");
   if (workspace_bytes < L.bytes)
     return fail(SFHK_E_NOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, L.bytes);
@@ -439,40 +539,9 @@ sfhk_status sfhk_propagate(const sfhk_problem* probs, int32_t n_prob, const sfhk
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace ws = carve(workspace, L);
   if ((st = stage_problems(descs, ws, nullptr, max_steps, s)) != SFHK_OK) return st;
-  // one wavefront per 64-lane pack; packs never straddle problems
-  const uint64_t max_packs = (ens->capacity + kWave - 1) / kWave + (uint64_t)n_prob;
-  if (max_packs > 0x7fffffffull) return fail(SFHK_E_UNSUPPORTED, "ensemble too large");
-  EnsPtrs ep = ens_ptrs(ens);
-  hipError_t e;
-  if (precision == SFHK_FP64) {
-    e = launch_propagate_f64(ws.descs, n_prob, ws.field, ep, nullptr, (uint32_t)max_packs, accum,
-                             final_state, ens->capacity, s, LaunchCfg{});
-  } else {
-    // FP32 stepping for every trajectory; those whose monodromy matrix grows
-    // past the FP32 bound are handed over, at that step, to an FP64 re-run
-    // from their birth (sorted into packs of their own).
-    e = launch_fill_i32(ws.redo, -1, ens->capacity, s);
-    if (e == hipSuccess)
-      e = launch_propagate_mixed(ws.descs, n_prob, ws.field, ep, ws.redo, (uint32_t)max_packs,
-                                 accum, final_state, ens->capacity, s, LaunchCfg{});
-    if (e == hipSuccess) e = launch_fill_u32(ws.hist, 0u, L.n_bins + 1, s);
-    if (e == hipSuccess) e = launch_count(ws.descs, ens->capacity, ep, ws.redo, ws.hist, s);
-    PackOut po{ws.order2, ws.runs2, ws.runs2 + n_prob, ws.runs2 + 2 * n_prob};
-    if (e == hipSuccess)
-      e = launch_sort(ws.descs, n_prob, ens->capacity, L.n_bins, ws.hist, ws.cursor, ep, ws.redo,
-                      po, s);
-    if (e == hipSuccess) {
-      EnsPtrs e2 = ep;
-      e2.order = po.order;
-      e2.live_start = po.live_start;
-      e2.live_count = po.live_count;
-      e2.pack_start = po.pack_start;
-      e = launch_propagate_f64(ws.descs, n_prob, ws.field, e2, ws.redo, (uint32_t)max_packs,
-                               accum, final_state, ens->capacity, s, LaunchCfg{});
-    }
-  }
-  if (e != hipSuccess) return hip_fail(e, "propagate");
-  return ok();
+  return propagate_enqueue(n_prob, ens, precision, accum,
+                           make_records(ens, final_state, snapshots, n_snap, snap_every), ws, L,
+                           s);
 }
 
 sfhk_status sfhk_dipole(const sfhk_problem* probs, int32_t n_prob, const double* accum,
@@ -522,7 +591,7 @@ sfhk_status sfhk_return_steps(const sfhk_problem* probs, int32_t n_prob,
   if (ens->capacity > 0 && (!k_ret || !e_ret)) return fail(SFHK_E_INVALID, "outputs are null");
   std::vector<Desc> descs;
   int64_t max_steps = 0;
-  Layout L = build_layout(probs, n_prob, ens->capacity, &descs, &max_steps);
+  Layout L = build_layout(probs, n_prob, ens->capacity, &descs, &max_steps, false, SFHK_FP64);
   if (!workspace) return fail(SFHK_E_INVALID, "workspace is null");
   if (workspace_bytes < L.bytes)
     return fail(SFHK_E_NOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, L.bytes);
@@ -581,11 +650,16 @@ struct sfhk_plan {
            *queue2 = nullptr, *counter = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // measurement: events around the trajectory kernel (0, 1) and the FP64
+  // re-run (2, 3), recorded by sfhk_plan_run only
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool ran_timed = false;
 };
 
 namespace {
 
-sfhk_status plan_enqueue(sfhk_plan* P, hipStream_t s) {
+// timed: record the plan's measurement events (not in a graph recording).
+sfhk_status plan_enqueue(sfhk_plan* P, hipStream_t s, bool timed) {
   const int n_prob = P->n_prob;
   const Workspace& ws = P->ws;
   EnsPtrs ep = P->ens;
@@ -610,15 +684,23 @@ sfhk_status plan_enqueue(sfhk_plan* P, hipStream_t s) {
                           P->queue, s);
     if (e == hipSuccess) e = launch_fill_u32(P->counter, 0u, 2, s);
   }
+  auto mark = [&](int i) {
+    if (timed && e == hipSuccess) e = hipEventRecord(P->ev[i], s);
+  };
   if (e == hipSuccess) {
     if (P->precision == SFHK_FP64) {
-      e = launch_propagate_f64(ws.descs, n_prob, ws.field, ep, nullptr, mp, P->accum, nullptr,
-                               P->capacity, s, cfg);
+      mark(0);
+      if (e == hipSuccess)
+        e = launch_propagate_f64(ws.descs, n_prob, ws.field, ep, nullptr, mp, P->accum,
+                                 Records{}, s, cfg);
+      mark(1);
     } else {
       e = launch_fill_i32(ws.redo, -1, P->capacity, s);
+      mark(0);
       if (e == hipSuccess)
         e = launch_propagate_mixed(ws.descs, n_prob, ws.field, ep, ws.redo, mp, P->accum,
-                                   nullptr, P->capacity, s, cfg);
+                                   Records{}, s, cfg);
+      mark(1);
       if (e == hipSuccess) e = launch_fill_u32(ws.hist, 0u, P->L.n_bins + 1, s);
       if (e == hipSuccess) e = launch_count(ws.descs, P->n_slots, ep, ws.redo, ws.hist, s);
       PackOut p2{ws.order2, ws.runs2, ws.runs2 + n_prob, ws.runs2 + 2 * n_prob};
@@ -636,9 +718,11 @@ sfhk_status plan_enqueue(sfhk_plan* P, hipStream_t s) {
       if (e == hipSuccess && cfg.persistent)
         e = launch_pack_queue(ws.descs, n_prob, e2, mp, P->L.n_len, P->qkeys, P->qhist,
                               P->qcursor, P->queue2, s);
+      mark(2);
       if (e == hipSuccess)
-        e = launch_propagate_f64(ws.descs, n_prob, ws.field, e2, ws.redo, mp, P->accum, nullptr,
-                                 P->capacity, s, cfg2);
+        e = launch_propagate_f64(ws.descs, n_prob, ws.field, e2, ws.redo, mp, P->accum,
+                                 Records{}, s, cfg2);
+      mark(3);
     }
   }
   if (e == hipSuccess)
@@ -745,6 +829,14 @@ sfhk_status sfhk_plan_create(const sfhk_problem* probs, int32_t n_prob,
   P->queue2 = reinterpret_cast<uint32_t*>(b + P->L.off_queue2);
   P->counter = reinterpret_cast<uint32_t*>(b + P->L.off_counter);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  for (hipEvent_t& ev : P->ev) {
+    e = hipEventCreate(&ev);
+    if (e != hipSuccess) {
+      for (hipEvent_t& x : P->ev)
+        if (x) hipEventDestroy(x);
+      return hip_fail(e, "plan events");
+    }
+  }
   if ((st = stage_problems(P->descs, P->ws, &slot_off, P->max_steps, s)) != SFHK_OK) return st;
   // the host copy of the descriptors must outlive the asynchronous upload
   e = hipStreamSynchronize(s);
@@ -755,7 +847,8 @@ sfhk_status sfhk_plan_create(const sfhk_problem* probs, int32_t n_prob,
 
 sfhk_status sfhk_plan_run(sfhk_plan* plan, void* stream) {
   if (!plan) return fail(SFHK_E_INVALID, "plan is null");
-  sfhk_status st = plan_enqueue(plan, static_cast<hipStream_t>(stream));
+  sfhk_status st = plan_enqueue(plan, static_cast<hipStream_t>(stream), true);
+  if (st == SFHK_OK) plan->ran_timed = true;
   return st == SFHK_OK ? ok() : st;
 }
 
@@ -773,7 +866,7 @@ sfhk_status sfhk_plan_capture(sfhk_plan* plan, void* stream) {
   }
   hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "begin capture");
-  sfhk_status st = plan_enqueue(plan, s);
+  sfhk_status st = plan_enqueue(plan, s, false);
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(s, &g);
   if (st != SFHK_OK) {
@@ -798,10 +891,23 @@ sfhk_status sfhk_plan_replay(sfhk_plan* plan, void* stream) {
   return ok();
 }
 
+sfhk_status sfhk_plan_kernel_ms(sfhk_plan* plan, float ms[2]) {
+  if (!plan || !ms) return fail(SFHK_E_INVALID, "plan and ms must be non-null");
+  if (!plan->ran_timed) return fail(SFHK_E_INVALID, "the plan has not been run with sfhk_plan_run");
+  ms[0] = ms[1] = 0.0f;
+  hipError_t e = hipEventElapsedTime(&ms[0], plan->ev[0], plan->ev[1]);
+  if (e == hipSuccess && plan->precision == SFHK_MIXED)
+    e = hipEventElapsedTime(&ms[1], plan->ev[2], plan->ev[3]);
+  if (e != hipSuccess) return hip_fail(e, "plan kernel times");
+  return ok();
+}
+
 void sfhk_plan_destroy(sfhk_plan* plan) {
   if (!plan) return;
   if (plan->exec) hipGraphExecDestroy(plan->exec);
   if (plan->graph) hipGraphDestroy(plan->graph);
+  for (hipEvent_t ev : plan->ev)
+    if (ev) hipEventDestroy(ev);
   delete plan;
 }
 

@@ -436,10 +436,12 @@ __device__ __forceinline__ void apply_step_matrix(const StepMatrix<T>& P, const 
 // and Mpp[:, c]).  The next column is loaded before the current one is
 // computed, so that the LDS latency is hidden behind its arithmetic; the
 // scheduling barrier per column bounds the registers in flight.
-template <int W>
+// With Track, mmax is raised to the largest |entry| of the new matrix.
+template <int W, bool Track = false>
 __device__ __forceinline__ void monodromy_step(const StepMatrix<double>& P, double (*mono)[W],
                                                int lane, double gamma, double inv_gamma,
-                                               double Rr[3][3], double Ri[3][3]) {
+                                               double Rr[3][3], double Ri[3][3],
+                                               double* mmax = nullptr) {
   double x[3] = {mono[0][lane], mono[6][lane], mono[12][lane]};
   double v[3] = {mono[18][lane], mono[24][lane], mono[30][lane]};
 #pragma unroll
@@ -466,10 +468,39 @@ __device__ __forceinline__ void monodromy_step(const StepMatrix<double>& P, doub
         Rr[r][c - 3] += vn[r];
         Ri[r][c - 3] -= gamma * xn[r];
       }
+      if constexpr (Track) *mmax = fmax(*mmax, fmax(fabs(xn[r]), fabs(vn[r])));
       x[r] = xl[r];
       v[r] = vl[r];
     }
   }
+}
+
+// One per-slot record (SFHK_FS_* layout, field-major with stride st) of the
+// state at one grid step; M is read from the LDS monodromy (element-major,
+// lane-minor) of either precision.
+template <typename TM, typename TS>
+__device__ __forceinline__ void write_record(double* __restrict__ f, uint64_t st,
+                                             const TS q[3], const TS p[3], TM (*mono)[kWave],
+                                             int lane, double S, double Cre, double Cim,
+                                             double flips, double mmax, double n_near) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    f[(SFHK_FS_Q + a) * st] = (double)q[a];
+    f[(SFHK_FS_P + a) * st] = (double)p[a];
+  }
+#pragma unroll
+  for (int i = 0; i < 36; ++i) f[(SFHK_FS_M + i) * st] = (double)mono[i][lane];
+  f[SFHK_FS_S * st] = S;
+  f[SFHK_FS_CRE * st] = Cre;
+  f[SFHK_FS_CIM * st] = Cim;
+  f[SFHK_FS_FLIPS * st] = flips;
+  f[SFHK_FS_MMAX * st] = mmax;
+  f[SFHK_FS_NEAR * st] = n_near;
+}
+
+// First snapshot step at or after k: the next multiple of every.
+__device__ __forceinline__ int first_snap_step(int k, int every) {
+  return ((k + every - 1) / every) * every;
 }
 
 // x from lane (lane ^ m) within each 32-lane half (ds_swizzle, bit-mask
@@ -580,10 +611,13 @@ __device__ __forceinline__ void prefactor_step(const double R2r[3][3], const dou
 // shell (the primitives of one centre and exponent share the Gaussian
 // factor).  Shells below the far-field cut are skipped (their terms are
 // < 3e-16).
+// near is set when at least one shell passes the far-field cut (the step
+// evaluates the recombination sum).
 __device__ __forceinline__ double amplitude_re(const Desc& d, const double n[3],
                                                const double p[3], const Geom<double>& G,
                                                double Cre, double Cim, double S, double tk,
-                                               double t0, double p0q0, double w) {
+                                               double t0, double p0q0, double w, bool& near) {
+  near = false;
   const double pp = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
   // |R_a - q|^2 from the softened distances of the geometry at q
   const double dd[2] = {G.r2[0] - d.eps2[0], G.r2[1] - d.eps2[1]};
@@ -611,6 +645,7 @@ __device__ __forceinline__ double amplitude_re(const Desc& d, const double n[3],
       const double i4 = d.sh_inv4k[j], i2 = 2.0 * i4;
       const double er = (bb_re_p - ddc) * i4 - ppg;  // <= 0
       if (er + lnC < kRecombFar) continue;
+      near = true;
       const double ei = 2.0 * pd * d.inv_gamma * i4;
       const double gm = exp_neg(-er);
       double sn, cs;

@@ -20,13 +20,14 @@ constexpr int kMonoElems = 36;  // row-major 6x6, rows (q, p), columns (q0, p0)
 // One 64-lane pack: every live lane runs its trajectory from its birth step
 // to t_N.  U consecutive steps are unrolled per loop trip.  VK: the screening
 // exponential's constants are kept in VGPRs (the per-pack kernel has the
-// registers; the persistent one would spill).
-template <int U, bool VK>
+// registers; the persistent one would spill).  Track: keep the running
+// monodromy maximum and the count of steps that evaluate the recombination
+// sum, and write the records asked for in rec.
+template <int U, bool VK, bool Track>
 __device__ __forceinline__ void run_pack(const Desc* __restrict__ descs,
                                          const double* __restrict__ field, const EnsPtrs& e,
                                          const int32_t* __restrict__ dep_from,
-                                         double* __restrict__ accum,
-                                         double* __restrict__ final_state, uint64_t capacity,
+                                         double* __restrict__ accum, const Records& rec,
                                          const Pack& pk, int lane, double (*mono)[kWave]) {
   const Desc& d = descs[pk.prob];
   const int N = d.N;
@@ -70,6 +71,9 @@ __device__ __forceinline__ void run_pack(const Desc* __restrict__ descs,
   ExpK ekv;
   if constexpr (VK) ekv = make_expk();
   const ExpK* ek = VK ? &ekv : nullptr;
+  double mmax = 1.0, n_near = 0.0;  // Track only
+  int snap_k = Track && rec.snap ? first_snap_step(kmin, rec.snap_every) : -1;
+  const int snap_end = Track && rec.snap ? rec.n_snap * rec.snap_every : 0;
 
   for (int kc = kmin; kc <= N; kc += U) {
 #pragma unroll
@@ -87,7 +91,18 @@ __device__ __forceinline__ void run_pack(const Desc* __restrict__ descs,
         kend = k;
         live = false;
       } else if (k >= kdep) {
-        re_a = amplitude_re(d, n, p, Gk, Cre, Cim, S, d.t_first + (double)k * h, t0, p0q0, w);
+        bool near;
+        re_a = amplitude_re(d, n, p, Gk, Cre, Cim, S, d.t_first + (double)k * h, t0, p0q0, w,
+                            near);
+        if constexpr (Track) n_near += near ? 1.0 : 0.0;
+      }
+    }
+    if constexpr (Track) {
+      if (k == snap_k && k < snap_end) {  // wave-uniform
+        if (valid && k >= k0 && k <= kend)
+          write_record(rec.snap + (uint64_t)(k / rec.snap_every) * SFHK_FS_COUNT * rec.capacity +
+                           slot, rec.capacity, q, p, mono, lane, S, Cre, Cim, flips, mmax, n_near);
+        snap_k += rec.snap_every;
       }
     }
     deposit(re_a, k, N, lane, acc_reg, acc);
@@ -160,37 +175,27 @@ __device__ __forceinline__ void run_pack(const Desc* __restrict__ descs,
     // columns c and c + 3 give column c of R.
     StepMatrix<double> P;
     rk4_step_matrix(K1, K2, K3, K4, h, P);
-    monodromy_step(P, mono, lane, d.gamma, d.inv_gamma, Rr, Ri);
+    monodromy_step<kWave, Track>(P, mono, lane, d.gamma, d.inv_gamma, Rr, Ri, &mmax);
   }
   }
 
-  if (final_state != nullptr && valid) {
-    double* f = final_state + slot;
-    const uint64_t st = capacity;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      f[(SFHK_FS_Q + a) * st] = q[a];
-      f[(SFHK_FS_P + a) * st] = p[a];
-    }
-#pragma unroll
-    for (int i = 0; i < kMonoElems; ++i) f[(SFHK_FS_M + i) * st] = mono[i][lane];
-    f[SFHK_FS_S * st] = S;
-    f[SFHK_FS_CRE * st] = Cre;
-    f[SFHK_FS_CIM * st] = Cim;
-    f[SFHK_FS_FLIPS * st] = flips;
+  if constexpr (Track) {
+    if (rec.final_state != nullptr && valid)
+      write_record(rec.final_state + slot, rec.capacity, q, p, mono, lane, S, Cre, Cim, flips,
+                   mmax, n_near);
   }
 }
 
-template <int U>
+template <int U, bool Track>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2)))
 propagate_f64_kernel(const Desc* __restrict__ descs, int n_prob, const double* __restrict__ field,
                      EnsPtrs e, const int32_t* __restrict__ dep_from, double* __restrict__ accum,
-                     double* __restrict__ final_state, uint64_t capacity) {
+                     Records rec) {
   __shared__ double mono[kMonoElems][kWave];
   const int lane = threadIdx.x;
   Pack pk;
   if (!find_pack(e, n_prob, blockIdx.x, lane, pk)) return;
-  run_pack<U, true>(descs, field, e, dep_from, accum, final_state, capacity, pk, lane, mono);
+  run_pack<U, true, Track>(descs, field, e, dep_from, accum, rec, pk, lane, mono);
 }
 
 // Persistent form: a fixed grid of wavefronts pulls pack indices from
@@ -200,7 +205,6 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2
 propagate_f64_persistent(const Desc* __restrict__ descs, int n_prob,
                          const double* __restrict__ field, EnsPtrs e,
                          const int32_t* __restrict__ dep_from, double* __restrict__ accum,
-                         double* __restrict__ final_state, uint64_t capacity,
                          const uint32_t* __restrict__ queue, uint32_t* __restrict__ counter) {
   __shared__ double mono[kMonoElems][kWave];
   const int lane = threadIdx.x;
@@ -212,7 +216,7 @@ propagate_f64_persistent(const Desc* __restrict__ descs, int n_prob,
     if (idx >= total) break;
     Pack pk;
     find_pack(e, n_prob, queue[idx], lane, pk);
-    run_pack<U, false>(descs, field, e, dep_from, accum, final_state, capacity, pk, lane, mono);
+    run_pack<U, false, false>(descs, field, e, dep_from, accum, Records{}, pk, lane, mono);
   }
 }
 
@@ -220,25 +224,26 @@ propagate_f64_persistent(const Desc* __restrict__ descs, int n_prob,
 
 hipError_t launch_propagate_f64(const Desc* descs, int n_prob, const double* field, EnsPtrs e,
                                 const int32_t* dep_from, uint32_t max_packs, double* accum,
-                                double* final_state, uint64_t capacity, hipStream_t s,
-                                const LaunchCfg& cfg) {
+                                const Records& rec, hipStream_t s, const LaunchCfg& cfg) {
   if (max_packs == 0) return hipSuccess;
   auto persistent = [&](auto kernel) {
     hipLaunchKernelGGL(kernel, dim3(cfg.grid), dim3(kWave), 0, s, descs, n_prob, field, e,
-                       dep_from, accum, final_state, capacity, cfg.queue, cfg.counter);
+                       dep_from, accum, cfg.queue, cfg.counter);
   };
   auto per_pack = [&](auto kernel) {
     hipLaunchKernelGGL(kernel, dim3(max_packs), dim3(kWave), 0, s, descs, n_prob, field, e,
-                       dep_from, accum, final_state, capacity);
+                       dep_from, accum, rec);
   };
-  if (cfg.persistent) {
+  if (rec.any()) {
+    per_pack(propagate_f64_kernel<1, true>);
+  } else if (cfg.persistent) {
     if (cfg.unroll == 4) persistent(propagate_f64_persistent<4>);
     else if (cfg.unroll == 2) persistent(propagate_f64_persistent<2>);
     else persistent(propagate_f64_persistent<1>);
   } else {
-    if (cfg.unroll == 4) per_pack(propagate_f64_kernel<4>);
-    else if (cfg.unroll == 2) per_pack(propagate_f64_kernel<2>);
-    else per_pack(propagate_f64_kernel<1>);
+    if (cfg.unroll == 4) per_pack(propagate_f64_kernel<4, false>);
+    else if (cfg.unroll == 2) per_pack(propagate_f64_kernel<2, false>);
+    else per_pack(propagate_f64_kernel<1, false>);
   }
   return hipGetLastError();
 }

@@ -46,13 +46,15 @@ __device__ __forceinline__ float monodromy_step_f32(const StepMatrix<float>& P,
   return mmax;
 }
 
-template <int U>
+// Track: keep the running monodromy maximum and the count of steps that
+// evaluate the recombination sum, and write the records asked for in rec
+// (those of trajectories handed to the FP64 re-run are rewritten by it).
+template <int U, bool Track>
 __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
                                                const double* __restrict__ field,
                                                const EnsPtrs& e, int32_t* __restrict__ redo,
-                                               double* __restrict__ accum,
-                                               double* __restrict__ final_state,
-                                               uint64_t capacity, const Pack& pk, int lane,
+                                               double* __restrict__ accum, const Records& rec,
+                                               const Pack& pk, int lane,
                                                float (*mono)[kWave]) {
   const Desc& d = descs[pk.prob];
   const int N = d.N;
@@ -84,6 +86,10 @@ __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
   const int kmin = __builtin_amdgcn_readfirstlane(k0);
   double acc_reg = 0.0;
   int kend = N + 1;  // first step not run here (handed to the FP64 re-run)
+  float mmax_all = 1.0f;
+  double n_near = 0.0;  // Track only
+  int snap_k = Track && rec.snap ? first_snap_step(kmin, rec.snap_every) : -1;
+  const int snap_end = Track && rec.snap ? rec.n_snap * rec.snap_every : 0;
 
   for (int kc = kmin; kc <= N; kc += U) {
 #pragma unroll
@@ -121,8 +127,19 @@ __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
         const double hRnd[3] = {d.half_R * n[0], d.half_R * n[1], d.half_R * n[2]};
         Geom<double> Gd;
         geometry(d, hRnd, qd_, Gd);
+        bool near;
         re_a = amplitude_re(d, n, pd_, Gd, Cre, Cim, S, d.t_first + (double)k * hd, t0, p0q0,
-                            w);
+                            w, near);
+        if constexpr (Track) n_near += near ? 1.0 : 0.0;
+      }
+    }
+    if constexpr (Track) {
+      if (k == snap_k && k < snap_end) {  // wave-uniform
+        if (valid && k >= k0 && k < kend)
+          write_record(rec.snap + (uint64_t)(k / rec.snap_every) * SFHK_FS_COUNT * rec.capacity +
+                           slot, rec.capacity, q, p, mono, lane, S, Cre, Cim, flips,
+                       (double)mmax_all, n_near);
+        snap_k += rec.snap_every;
       }
     }
     deposit(re_a, k, N, lane, acc_reg, acc);
@@ -191,6 +208,7 @@ __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
     StepMatrix<float> P;
     rk4_step_matrix<float, true>(K1, K2, K3, K4, h, P);
     const float mmax = monodromy_step_f32(P, mono, lane);
+    if constexpr (Track) mmax_all = fmaxf(mmax_all, mmax);
     // FP32 rounding is amplified by the monodromy matrix: past the bound the
     // trajectory is finished by the FP64 kernel from step k + 1 on
     if (mmax > kMixedFlagNorm) {
@@ -201,34 +219,23 @@ __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
   }
 
   // trajectories handed to the FP64 re-run get their final state from it
-  if (final_state != nullptr && valid && kend > N) {
-    double* f = final_state + slot;
-    const uint64_t st = capacity;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      f[(SFHK_FS_Q + a) * st] = (double)q[a];
-      f[(SFHK_FS_P + a) * st] = (double)p[a];
-    }
-#pragma unroll
-    for (int i = 0; i < kMonoElems; ++i) f[(SFHK_FS_M + i) * st] = (double)mono[i][lane];
-    f[SFHK_FS_S * st] = S;
-    f[SFHK_FS_CRE * st] = Cre;
-    f[SFHK_FS_CIM * st] = Cim;
-    f[SFHK_FS_FLIPS * st] = flips;
+  if constexpr (Track) {
+    if (rec.final_state != nullptr && valid && kend > N)
+      write_record(rec.final_state + slot, rec.capacity, q, p, mono, lane, S, Cre, Cim, flips,
+                   (double)mmax_all, n_near);
   }
 }
 
-template <int U>
+template <int U, bool Track>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3, 3)))
 propagate_mixed_kernel(const Desc* __restrict__ descs, int n_prob,
                        const double* __restrict__ field, EnsPtrs e, int32_t* __restrict__ redo,
-                       double* __restrict__ accum, double* __restrict__ final_state,
-                       uint64_t capacity) {
+                       double* __restrict__ accum, Records rec) {
   __shared__ float mono[kMonoElems][kWave];
   const int lane = threadIdx.x;
   Pack pk;
   if (!find_pack(e, n_prob, blockIdx.x, lane, pk)) return;
-  run_pack_mixed<U>(descs, field, e, redo, accum, final_state, capacity, pk, lane, mono);
+  run_pack_mixed<U, Track>(descs, field, e, redo, accum, rec, pk, lane, mono);
 }
 
 template <int U>
@@ -236,7 +243,6 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3, 3
 propagate_mixed_persistent(const Desc* __restrict__ descs, int n_prob,
                            const double* __restrict__ field, EnsPtrs e,
                            int32_t* __restrict__ redo, double* __restrict__ accum,
-                           double* __restrict__ final_state, uint64_t capacity,
                            const uint32_t* __restrict__ queue, uint32_t* __restrict__ counter) {
   __shared__ float mono[kMonoElems][kWave];
   const int lane = threadIdx.x;
@@ -248,7 +254,7 @@ propagate_mixed_persistent(const Desc* __restrict__ descs, int n_prob,
     if (idx >= total) break;
     Pack pk;
     find_pack(e, n_prob, queue[idx], lane, pk);
-    run_pack_mixed<U>(descs, field, e, redo, accum, final_state, capacity, pk, lane, mono);
+    run_pack_mixed<U, false>(descs, field, e, redo, accum, Records{}, pk, lane, mono);
   }
 }
 
@@ -256,25 +262,26 @@ propagate_mixed_persistent(const Desc* __restrict__ descs, int n_prob,
 
 hipError_t launch_propagate_mixed(const Desc* descs, int n_prob, const double* field, EnsPtrs e,
                                   int32_t* redo, uint32_t max_packs, double* accum,
-                                  double* final_state, uint64_t capacity, hipStream_t s,
-                                  const LaunchCfg& cfg) {
+                                  const Records& rec, hipStream_t s, const LaunchCfg& cfg) {
   if (max_packs == 0) return hipSuccess;
   auto persistent = [&](auto kernel) {
     hipLaunchKernelGGL(kernel, dim3(cfg.grid), dim3(kWave), 0, s, descs, n_prob, field, e, redo,
-                       accum, final_state, capacity, cfg.queue, cfg.counter);
+                       accum, cfg.queue, cfg.counter);
   };
   auto per_pack = [&](auto kernel) {
     hipLaunchKernelGGL(kernel, dim3(max_packs), dim3(kWave), 0, s, descs, n_prob, field, e, redo,
-                       accum, final_state, capacity);
+                       accum, rec);
   };
-  if (cfg.persistent) {
+  if (rec.any()) {
+    per_pack(propagate_mixed_kernel<1, true>);
+  } else if (cfg.persistent) {
     if (cfg.unroll == 4) persistent(propagate_mixed_persistent<4>);
     else if (cfg.unroll == 2) persistent(propagate_mixed_persistent<2>);
     else persistent(propagate_mixed_persistent<1>);
   } else {
-    if (cfg.unroll == 4) per_pack(propagate_mixed_kernel<4>);
-    else if (cfg.unroll == 2) per_pack(propagate_mixed_kernel<2>);
-    else per_pack(propagate_mixed_kernel<1>);
+    if (cfg.unroll == 4) per_pack(propagate_mixed_kernel<4, false>);
+    else if (cfg.unroll == 2) per_pack(propagate_mixed_kernel<2, false>);
+    else per_pack(propagate_mixed_kernel<1, false>);
   }
   return hipGetLastError();
 }

@@ -104,7 +104,9 @@ serve_slice_f64(const ReqDev* __restrict__ reqs, SliceTable tab) {
         kend = k;
         live = false;
       } else {
-        re_a = amplitude_re(d, n, p, Gk, Cre, Cim, S, d.t_first + (double)k * h, t0, p0q0, w8);
+        bool near;
+        re_a = amplitude_re(d, n, p, Gk, Cre, Cim, S, d.t_first + (double)k * h, t0, p0q0, w8,
+                            near);
       }
     }
     deposit(re_a, k, N, lane, acc_reg, acc);

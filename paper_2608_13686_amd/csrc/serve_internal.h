@@ -5,10 +5,11 @@
 
 namespace sfhk {
 
-// Per-trajectory state saved between windows: the SFHK_FS_* fields plus the
-// step at which the prefactor cap stopped the trajectory.
-constexpr int kStateKend = SFHK_FS_COUNT;
-constexpr int kStateFields = SFHK_FS_COUNT + 1;
+// Per-trajectory state saved between windows: the SFHK_FS_* fields up to the
+// branch-flip count, plus the step at which the prefactor cap stopped the
+// trajectory.
+constexpr int kStateKend = SFHK_FS_FLIPS + 1;
+constexpr int kStateFields = kStateKend + 1;
 
 // One request's device view: its problem constants and the device buffers
 // carved from its slice of the pool (one problem, so offsets are 0).

@@ -145,16 +145,26 @@ struct LaunchCfg {
   uint32_t* counter = nullptr;
 };
 
+// Optional per-slot records of a propagation (SFHK_FS_* layout, field-major,
+// stride capacity): the final state, and the state at the grid steps
+// k = s snap_every (s < n_snap) that the trajectory reaches.  Any record
+// selects the one-pack-per-wavefront kernel that keeps them.
+struct Records {
+  double* final_state = nullptr;  // [SFHK_FS_COUNT][capacity]
+  double* snap = nullptr;         // [n_snap][SFHK_FS_COUNT][capacity]
+  int32_t n_snap = 0, snap_every = 1;
+  uint64_t capacity = 0;
+  bool any() const { return final_state != nullptr || snap != nullptr; }
+};
+
 // dep_from (nullable, per slot): deposit amplitudes only from that step on.
 hipError_t launch_propagate_f64(const Desc* descs, int n_prob, const double* field, EnsPtrs e,
                                 const int32_t* dep_from, uint32_t max_packs, double* accum,
-                                double* final_state, uint64_t capacity, hipStream_t s,
-                                const LaunchCfg& cfg);
+                                const Records& rec, hipStream_t s, const LaunchCfg& cfg);
 // redo (per slot, preset to -1): set to the first step left to the FP64 re-run.
 hipError_t launch_propagate_mixed(const Desc* descs, int n_prob, const double* field, EnsPtrs e,
                                   int32_t* redo, uint32_t max_packs, double* accum,
-                                  double* final_state, uint64_t capacity, hipStream_t s,
-                                  const LaunchCfg& cfg);
+                                  const Records& rec, hipStream_t s, const LaunchCfg& cfg);
 // Pack queue ordered by remaining steps (longest first), ties by pack id:
 // queue[max_packs]; keys, hist, cursor: scratch of max_packs, n_len + 1, n_len + 1
 // entries with n_len = max_P N_P + 1.

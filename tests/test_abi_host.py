@@ -40,7 +40,7 @@ def test_library_exports_every_header_symbol(L):
 
 
 def test_abi_version(L):
-    assert L.lib().sfhk_abi_version() == 2
+    assert L.lib().sfhk_abi_version() == 3
 
 
 def test_ionisation_step_validated(L):
@@ -122,11 +122,19 @@ def test_entry_points_validate_before_enqueueing(L):
     assert lib.sfhk_sample_initial(p, 1, one, one, one, C.byref(ens), None, 0, None) == 1
     assert lib.sfhk_sample_initial(None, 1, one, one, one, C.byref(ens), None, 0, None) == 1
     assert lib.sfhk_sample_initial(p, 0, one, one, one, C.byref(ens), None, 0, None) == 1
-    assert lib.sfhk_propagate(p, 1, C.byref(ens), 0, None, None, None, 0, None) == 1
-    assert lib.sfhk_propagate(p, 1, None, 0, None, None, None, 0, None) == 1
+    assert lib.sfhk_propagate(p, 1, C.byref(ens), 0, None, None, None, 0, 1, None, 0, None) == 1
+    assert lib.sfhk_propagate(p, 1, None, 0, None, None, None, 0, 1, None, 0, None) == 1
     e0 = _abi.Ensemble()  # capacity 0, but bad precision
-    assert lib.sfhk_propagate(p, 1, C.byref(e0), 9, C.c_void_p(8), None, C.c_void_p(8), 1 << 30,
-                              None) == 1
+    assert lib.sfhk_propagate(p, 1, C.byref(e0), 9, C.c_void_p(8), None, None, 0, 1,
+                              C.c_void_p(8), 1 << 30, None) == 1
+    # snapshots need a count and a stride
+    for n_snap, every in ((0, 1), (3, 0), (-1, 5)):
+        assert lib.sfhk_propagate(p, 1, C.byref(e0), 0, C.c_void_p(8), None, C.c_void_p(8),
+                                  n_snap, every, C.c_void_p(8), 1 << 30, None) == 1
+        assert b"snap" in lib.sfhk_last_error()
+    # an empty ensemble is a valid no-op, with or without records
+    assert lib.sfhk_propagate(p, 1, C.byref(e0), 0, C.c_void_p(8), None, C.c_void_p(8), 2, 5,
+                              C.c_void_p(8), 1 << 30, None) == 0
     assert lib.sfhk_dipole(p, 1, None, one, None, None) == 1
     assert lib.sfhk_spectrum(None, 0, 0.0, 0.1, 1.0, None, 1, None, None, None, None) == 1
     assert lib.sfhk_spectrum(None, 10, 0.0, -0.1, 1.0, None, 1, None, None, None, None) == 1
@@ -156,6 +164,30 @@ def test_capacity_and_workspace_size_errors(L):
     n = _abi.u64_array([8])
     assert lib.sfhk_sample_initial(p, 1, n, n, n, C.byref(ens), C.c_void_p(64), 16, None) == 2
     assert b"workspace" in lib.sfhk_last_error()
+
+
+def test_footprint_bytes(L):
+    """The footprint counts the ensemble (100 B of arrays per slot), the
+    workspace of the precision (field table 16 B and sort bins 8 B per step;
+    the mixed one adds the 8 B per slot of the FP64 hand-over) and accum + v
+    (16 B per step); invalid arguments give 0."""
+    from paper_2608_13686_amd import _abi
+    import paper_2608_13686_amd as sf
+    p = workloads.n2(0.0)
+    N = sf.problem_steps(p)[0]
+    n = 1 << 20
+    f64 = sf.footprint_bytes(p, n, "fp64")
+    mix = sf.footprint_bytes(p, n, "mixed")
+    lo = 100 * n + 32 * (N + 1) + 8 * (N + 2)
+    assert lo < f64 < lo + 16384
+    assert mix - f64 >= 8 * n and mix - f64 < 8 * n + 4096
+    assert f64 < sf.footprint_bytes(p, n + 64, "fp64")
+    assert sf.footprint_bytes(p, 0, "fp64") > 0
+    lib = L.lib()
+    arr = _abi.make_problems([p])
+    assert lib.sfhk_footprint_bytes(arr, n, 7) == 0
+    assert lib.sfhk_footprint_bytes(arr, 1 << 33, 0) == 0
+    assert lib.sfhk_footprint_bytes(None, n, 0) == 0
 
 
 def test_gabor_arguments_validated(L):

