@@ -244,6 +244,26 @@ sfhk_status sfhk_propagate(const sfhk_problem* probs, int32_t n_prob, const sfhk
                            double* snapshots, int32_t n_snap, int32_t snap_every,
                            void* workspace, size_t workspace_bytes, void* stream);
 
+/* sfhk_propagate without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the workspace is a 32 MiB array of the
+ * library in each GPU's memory, reserved when the library is loaded on that
+ * GPU and held until the process ends.  Arguments and results as for
+ * sfhk_propagate; problem descriptors travel as kernel arguments.  The call
+ * allocates no device memory and calls no allocating HIP or library routine.
+ * Limits: at most 1024 problems, and at most 32 MiB of workspace need (that
+ * of sfhk_propagate at this precision, at most sfhk_workspace_bytes: about
+ * 24 B per step and problem plus, for SFHK_MIXED, 8 B per slot); beyond them
+ * SFHK_E_NOMEM with a message, before anything is enqueued.  Every call on a
+ * GPU uses that GPU's one array and leaves its contents behind: calls that
+ * overlap on one GPU (on different streams, or from different threads
+ * without ordering) race and give wrong results; calls ordered on one
+ * stream do not. */
+sfhk_status sfhk_propagate_static(const sfhk_problem* probs, int32_t n_prob,
+                                  const sfhk_ensemble* ens, int32_t precision, double* accum,
+                                  double* final_state, double* snapshots, int32_t n_snap,
+                                  int32_t snap_every, void* stream);
+
 /* Dipole velocity (Sec. II.A, Eq. 4-6): v_k = (2 / n_sampled[P]) accum_k for
  * each problem (n_sampled counts dropped trajectories too).
  * accum, v_out: device double, the accum layout; n_sampled: host [n_prob]. */

@@ -14,7 +14,7 @@ STATUS = {0: "SFHK_OK", 1: "SFHK_E_INVALID", 2: "SFHK_E_NOMEM", 3: "SFHK_E_DEVIC
           4: "SFHK_E_BUSY", 5: "SFHK_E_UNSUPPORTED"}
 
 EXPORTS = ["sfhk_abi_version", "sfhk_last_error", "sfhk_problem_steps", "sfhk_workspace_bytes",
-           "sfhk_footprint_bytes",
+           "sfhk_footprint_bytes", "sfhk_propagate_static",
            "sfhk_sample_initial", "sfhk_propagate", "sfhk_dipole", "sfhk_spectrum",
            "sfhk_plan_workspace_bytes", "sfhk_plan_create", "sfhk_plan_run", "sfhk_plan_capture",
            "sfhk_plan_replay", "sfhk_plan_destroy", "sfhk_plan_kernel_ms", "sfhk_request_bytes", "sfhk_request_layout",
@@ -99,6 +99,10 @@ def lib():
                                      C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                      C.c_void_p, C.c_size_t, C.c_void_p]
         L.sfhk_propagate.restype = C.c_int
+        L.sfhk_propagate_static.argtypes = [P, C.c_int32, C.POINTER(Ensemble), C.c_int32,
+                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                            C.c_int32, C.c_void_p]
+        L.sfhk_propagate_static.restype = C.c_int
         L.sfhk_dipole.argtypes = [P, C.c_int32, C.c_void_p, u64p, C.c_void_p, C.c_void_p]
         L.sfhk_dipole.restype = C.c_int
         L.sfhk_spectrum.argtypes = [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double,

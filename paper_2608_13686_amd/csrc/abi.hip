@@ -7,6 +7,7 @@
 #include <cstring>
 #include <string>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -342,6 +343,46 @@ sfhk_status stage_problems(const std::vector<Desc>& descs, const Workspace& ws,
   return SFHK_OK;
 }
 
+// The same staging with the descriptors passed as kernel arguments (one
+// small kernel per problem), so that no host memory is read after the call.
+sfhk_status stage_problems_by_args(const std::vector<Desc>& descs, const Workspace& ws,
+                                   int64_t max_steps, hipStream_t s) {
+  for (size_t i = 0; i < descs.size(); ++i) {
+    hipError_t e = launch_store_desc(descs[i], ws.descs + i, s);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+  }
+  hipError_t e = launch_field(ws.descs, (int)descs.size(), ws.field, (uint64_t)max_steps + 1, s);
+  if (e != hipSuccess) return hip_fail(e, "field table");
+  return SFHK_OK;
+}
+
+// Workspace of sfhk_propagate_static: a device array of the library, one
+// copy per GPU, that lives until the process ends.  Host code never uses its
+// name as an address: the device address of each GPU's copy is looked up
+// once, with that GPU current, and kept.
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+constexpr int kStaticMaxProblems = 1024;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+sfhk_status static_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "current device");
+  if (dev < 0 || dev >= kMaxDevices) return fail(SFHK_E_UNSUPPORTED, "device index %d", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "static workspace address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SFHK_OK;
+}
+
 // Argument checks, descriptors and workspace layout of a propagation.
 sfhk_status propagate_prepare(const sfhk_problem* probs, int32_t n_prob, const sfhk_ensemble* ens,
                               int32_t precision, double* accum, double* snapshots,
@@ -539,6 +580,35 @@ sfhk_status sfhk_propagate(const sfhk_problem* probs, int32_t n_prob, const sfhk
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace ws = carve(workspace, L);
   if ((st = stage_problems(descs, ws, nullptr, max_steps, s)) != SFHK_OK) return st;
+  return propagate_enqueue(n_prob, ens, precision, accum,
+                           make_records(ens, final_state, snapshots, n_snap, snap_every), ws, L,
+                           s);
+}
+
+sfhk_status sfhk_propagate_static(const sfhk_problem* probs, int32_t n_prob,
+                                  const sfhk_ensemble* ens, int32_t precision, double* accum,
+                                  double* final_state, double* snapshots, int32_t n_snap,
+                                  int32_t snap_every, void* stream) {
+  std::vector<Desc> descs;
+  int64_t max_steps = 0;
+  Layout L;
+  sfhk_status st = propagate_prepare(probs, n_prob, ens, precision, accum, snapshots, n_snap,
+                                     snap_every, descs, max_steps, L);
+  if (st != SFHK_OK) return st;
+  if (n_prob > kStaticMaxProblems)
+    return fail(SFHK_E_NOMEM, "sfhk_propagate_static takes at most %d problems, got %d",
+                kStaticMaxProblems, n_prob);
+  if (L.bytes > kStaticScratchBytes)
+    return fail(SFHK_E_NOMEM,
+                "sfhk_propagate_static: these problems and %llu slots need %zu bytes of "
+                "workspace, the static workspace holds %zu",
+                (unsigned long long)ens->capacity, L.bytes, kStaticScratchBytes);
+  if (ens->capacity == 0) return ok();
+  void* base = nullptr;
+  if ((st = static_scratch(&base)) != SFHK_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace ws = carve(base, L);
+  if ((st = stage_problems_by_args(descs, ws, max_steps, s)) != SFHK_OK) return st;
   return propagate_enqueue(n_prob, ens, precision, accum,
                            make_records(ens, final_state, snapshots, n_snap, snap_every), ws, L,
                            s);

@@ -18,6 +18,13 @@ __global__ void fill_f64_kernel(double* __restrict__ p, double v, uint64_t n) {
   if (i < n) p[i] = v;
 }
 
+// One problem descriptor, passed by value, stored to device memory: the
+// upload reads no host memory after the launch call returns.
+static_assert(sizeof(Desc) <= 3840, "Desc is passed by value as a kernel argument");
+__global__ void store_desc_kernel(Desc d, Desc* __restrict__ dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = d;
+}
+
 // ---------------------------------------------------------------- field
 // E(t) = -dA/dt of A(t) = -(E0/w) cos^2(pi t/tau) sin(w t + cep) for
 // |t| <= tau/2, zero outside (sin^2 pulse of Sec. II.D / III.A, centred at
@@ -453,6 +460,11 @@ __global__ void __launch_bounds__(kBlock) gabor_kernel(const double* __restrict_
 }
 
 }  // namespace
+
+hipError_t launch_store_desc(const Desc& d, Desc* dst, hipStream_t s) {
+  hipLaunchKernelGGL(store_desc_kernel, dim3(1), dim3(1), 0, s, d, dst);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;

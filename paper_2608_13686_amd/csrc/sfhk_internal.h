@@ -122,6 +122,8 @@ hipError_t launch_sort(const Desc* descs, int n_prob, uint64_t n_slots, uint64_t
                        uint32_t* hist, uint32_t* cursor, EnsPtrs e, const int32_t* select,
                        PackOut out, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, uint64_t n, hipStream_t s);
+// Stores one descriptor, passed as a kernel argument, at dst.
+hipError_t launch_store_desc(const Desc& d, Desc* dst, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, uint64_t n, hipStream_t s);
 hipError_t launch_scale(const double* in, double* out, double scale, uint64_t n, hipStream_t s);
 hipError_t launch_returns(const Desc* descs, int n_prob, const double* field, EnsPtrs e,
