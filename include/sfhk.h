@@ -228,6 +228,10 @@ sfhk_status sfhk_sample_initial(const sfhk_problem* probs, int32_t n_prob,
  *          n_snap >= 1 and snap_every >= 1 when snapshots is non-null.
  *          Asking for either record runs the one-wavefront-per-pack kernel
  *          that keeps them (same arithmetic as without).
+ *   Launches of at most 128 64-lane packs (capacity <= 128 x 64 - n_prob
+ *   slots) run one trajectory per 8 lanes (latency form: same equations,
+ *   RK4 applied per monodromy column instead of through the RK4 step
+ *   matrix), and so does the FP64 re-run of the mixed form.
  *   precision: SFHK_FP64 (everything FP64) or SFHK_MIXED: q, p, the
  *          potential and its derivatives, the monodromy matrix and det R in
  *          FP32; S, the root of det R with its branch, the amplitude and the
@@ -319,8 +323,13 @@ typedef struct {
                             1: a persistent grid pulls packs, longest first, from a device queue */
   int32_t waves_per_cu;  /* persistent grid = 256 CUs x waves_per_cu wavefronts, 1..32 (0: 8) */
   int32_t step_unroll;   /* RK4 steps per loop trip: 1, 2 or 4 (0: 1) */
-  int32_t traj_per_lane; /* trajectories per lane: 1 (0: 1); the FP64 state of one trajectory
-                            already fills the register budget of two wavefronts per SIMD */
+  int32_t traj_per_lane; /* trajectories per lane: 1 (0: 1).  The FP64 state of one
+                            trajectory fills the register budget of two wavefronts per SIMD;
+                            two FP32 trajectories per lane would pay only through packed FP32
+                            arithmetic, which this build does not emit */
+  int32_t lanes_per_traj; /* lanes per trajectory of the FP64 re-run of trajectories the mixed
+                            form hands over: 1, or 8 for the latency form (one monodromy column
+                            per lane); 0: 8 */
 } sfhk_tuning;
 
 typedef struct sfhk_plan sfhk_plan;

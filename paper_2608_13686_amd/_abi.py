@@ -66,7 +66,8 @@ IONIZATION = {"first_order": 0, "saddle": 1, "saddle_modified": 2}
 
 class Tuning(C.Structure):
     _fields_ = [("persistent", C.c_int32), ("waves_per_cu", C.c_int32),
-                ("step_unroll", C.c_int32), ("traj_per_lane", C.c_int32)]
+                ("step_unroll", C.c_int32), ("traj_per_lane", C.c_int32),
+                ("lanes_per_traj", C.c_int32)]
 
 
 _lib = None

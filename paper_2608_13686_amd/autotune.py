@@ -2,10 +2,14 @@
 
 Times a plan's recorded graph for each candidate (persistent queue or one
 wavefront per pack, wavefronts per CU of the persistent grid, RK4 steps per
-loop trip) on the workload it will serve, keeps the fastest, and caches the
-choice as JSON per (GPU architecture, precision, potential kinds, GTO
-primitives).  Trajectories per lane is fixed at 1: the FP64 state of one
-trajectory already fills the register budget of two wavefronts per SIMD.
+loop trip) on the workload it will serve, keeps the fastest, then, for the
+mixed precision, times the fastest with the FP64 re-run of handed-over
+trajectories in each form (1 lane per trajectory, or the 8-lane latency
+form), and caches the choice as JSON per (GPU architecture, precision,
+potential kinds, GTO primitives).  Trajectories per lane is fixed at 1: the
+FP64 state of one trajectory already fills the register budget of two
+wavefronts per SIMD, and two FP32 trajectories per lane would pay only
+through packed FP32 arithmetic, which this build does not emit.
 
     python -m paper_2608_13686_amd.autotune --workload batched
 """
@@ -20,8 +24,9 @@ from . import Plan
 
 CACHE_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning")
 
-CANDIDATES = [(0, 8, u, 1) for u in (1, 2, 4)] + [(1, w, u, 1) for w in (4, 8, 12, 16)
-                                                    for u in (1, 2, 4)]
+CANDIDATES = [(0, 8, u, 1, 8) for u in (1, 2, 4)] + [(1, w, u, 1, 8) for w in (4, 8, 12, 16)
+                                                       for u in (1, 2, 4)]
+RERUN_LANES = (1, 8)
 
 
 def cache_key(probs, precision):
@@ -63,6 +68,16 @@ def tune(probs, n_traj, seeds, precision, candidates=CANDIDATES, reps=2, verbose
         if verbose:
             print(f"tuning {cand}: {t * 1e3:.1f} ms", flush=True)
     best = min(rows, key=lambda r: r["seconds"])
+    if precision == "mixed":
+        for lanes in RERUN_LANES:
+            cand = tuple(best["tuning"][:4]) + (lanes,)
+            if list(cand) == best["tuning"]:
+                continue
+            t = time_plan(probs, n_traj, seeds, precision, cand, reps)
+            rows.append({"tuning": list(cand), "seconds": t})
+            if verbose:
+                print(f"tuning {cand}: {t * 1e3:.1f} ms", flush=True)
+        best = min(rows, key=lambda r: r["seconds"])
     return {"key": cache_key(probs, precision), "best": best["tuning"], "table": rows,
             "workload": {"n_problems": len(probs), "n_traj": sum(n_traj)}}
 
@@ -72,7 +87,8 @@ def cached(probs, precision):
     path = os.path.join(CACHE_DIR, cache_key(probs, precision) + ".json")
     if not os.path.exists(path):
         return None
-    return tuple(json.load(open(path))["best"])
+    best = tuple(json.load(open(path))["best"])
+    return best if len(best) == 5 else best + (8,)  # choices kept before the lane knob
 
 
 def save(result, out_dir=CACHE_DIR):

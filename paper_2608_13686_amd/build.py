@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsfhk.so")
 OBJ = os.path.join(PKG, "_build")
 SOURCES = ["abi.hip", "setup_kernels.hip", "propagate_f64.hip", "propagate_mixed.hip",
-           "serve.hip", "serve_abi.hip", "analysis.hip"]
+           "propagate_latency.hip", "serve.hip", "serve_abi.hip", "analysis.hip"]
 ARCH = os.environ.get("SFHK_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -424,8 +424,14 @@ sfhk_status propagate_enqueue(int n_prob, const sfhk_ensemble* ens, int precisio
   EnsPtrs ep = ens_ptrs(ens);
   hipError_t e;
   if (precision == SFHK_FP64) {
-    e = launch_propagate_f64(ws.descs, n_prob, ws.field, ep, nullptr, (uint32_t)max_packs, accum,
-                             rec, s, LaunchCfg{});
+    // far below device fill a trajectory's step latency sets the time: the
+    // latency form (one trajectory per 8 lanes)
+    if (max_packs <= kLatencyMaxPacks)
+      e = launch_propagate_latency(ws.descs, n_prob, ws.field, ep, nullptr, (uint32_t)max_packs,
+                                   accum, rec, s, LaunchCfg{});
+    else
+      e = launch_propagate_f64(ws.descs, n_prob, ws.field, ep, nullptr, (uint32_t)max_packs,
+                               accum, rec, s, LaunchCfg{});
   } else {
     e = launch_fill_i32(ws.redo, -1, ens->capacity, s);
     if (e == hipSuccess)
@@ -443,8 +449,9 @@ sfhk_status propagate_enqueue(int n_prob, const sfhk_ensemble* ens, int precisio
       e2.live_start = po.live_start;
       e2.live_count = po.live_count;
       e2.pack_start = po.pack_start;
-      e = launch_propagate_f64(ws.descs, n_prob, ws.field, e2, ws.redo, (uint32_t)max_packs,
-                               accum, rec, s, LaunchCfg{});
+      // the handed-over trajectories are few: latency form
+      e = launch_propagate_latency(ws.descs, n_prob, ws.field, e2, ws.redo, (uint32_t)max_packs,
+                                   accum, rec, s, LaunchCfg{});
     }
   }
   if (e != hipSuccess) return hip_fail(e, "propagate");
@@ -713,6 +720,7 @@ struct sfhk_plan {
   uint64_t capacity = 0, n_slots = 0;
   int64_t max_steps = 0;
   uint32_t grid = 0;
+  uint32_t grid_latency = 0;  // persistent grid of the latency-form re-run
   double *accum = nullptr, *v = nullptr, *Vre = nullptr, *Vim = nullptr, *Y = nullptr;
   double h_step = 0.0;
   int n_omega = 0;
@@ -759,10 +767,14 @@ sfhk_status plan_enqueue(sfhk_plan* P, hipStream_t s, bool timed) {
   };
   if (e == hipSuccess) {
     if (P->precision == SFHK_FP64) {
+      // the same choice of form as sfhk_propagate: latency form far below fill
       mark(0);
       if (e == hipSuccess)
-        e = launch_propagate_f64(ws.descs, n_prob, ws.field, ep, nullptr, mp, P->accum,
-                                 Records{}, s, cfg);
+        e = mp <= kLatencyMaxPacks
+                ? launch_propagate_latency(ws.descs, n_prob, ws.field, ep, nullptr, mp, P->accum,
+                                           Records{}, s, cfg)
+                : launch_propagate_f64(ws.descs, n_prob, ws.field, ep, nullptr, mp, P->accum,
+                                       Records{}, s, cfg);
       mark(1);
     } else {
       e = launch_fill_i32(ws.redo, -1, P->capacity, s);
@@ -785,13 +797,17 @@ sfhk_status plan_enqueue(sfhk_plan* P, hipStream_t s, bool timed) {
       LaunchCfg cfg2 = cfg;
       cfg2.queue = P->queue2;
       cfg2.counter = P->counter + 1;
+      const bool lat = P->tune.lanes_per_traj == 8;
+      if (lat && cfg.persistent) cfg2.grid = P->grid_latency;
       if (e == hipSuccess && cfg.persistent)
         e = launch_pack_queue(ws.descs, n_prob, e2, mp, P->L.n_len, P->qkeys, P->qhist,
                               P->qcursor, P->queue2, s);
       mark(2);
       if (e == hipSuccess)
-        e = launch_propagate_f64(ws.descs, n_prob, ws.field, e2, ws.redo, mp, P->accum,
-                                 Records{}, s, cfg2);
+        e = lat ? launch_propagate_latency(ws.descs, n_prob, ws.field, e2, ws.redo, mp, P->accum,
+                                           Records{}, s, cfg2)
+                : launch_propagate_f64(ws.descs, n_prob, ws.field, e2, ws.redo, mp, P->accum,
+                                       Records{}, s, cfg2);
       mark(3);
     }
   }
@@ -836,15 +852,17 @@ sfhk_status sfhk_plan_create(const sfhk_problem* probs, int32_t n_prob,
   if (!accum || !v) return fail(SFHK_E_INVALID, "accum and v must be non-null");
   if (n_omega < 0 || (n_omega > 0 && (!V_re || !V_im || !yield || !(h_step >= 0.0))))
     return fail(SFHK_E_INVALID, "spectrum outputs invalid");
-  sfhk_tuning t{0, 8, 1, 1};
+  sfhk_tuning t{0, 8, 1, 1, 8};
   if (tuning) {
     t = *tuning;
     if (t.waves_per_cu == 0) t.waves_per_cu = 8;
     if (t.step_unroll == 0) t.step_unroll = 1;
     if (t.traj_per_lane == 0) t.traj_per_lane = 1;
+    if (t.lanes_per_traj == 0) t.lanes_per_traj = 8;
   }
   if ((t.persistent != 0 && t.persistent != 1) || t.waves_per_cu < 1 || t.waves_per_cu > 32 ||
-      (t.step_unroll != 1 && t.step_unroll != 2 && t.step_unroll != 4))
+      (t.step_unroll != 1 && t.step_unroll != 2 && t.step_unroll != 4) ||
+      (t.lanes_per_traj != 1 && t.lanes_per_traj != 8))
     return fail(SFHK_E_INVALID, "tuning out of range");
   if (t.traj_per_lane != 1)
     return fail(SFHK_E_UNSUPPORTED, "traj_per_lane %d: only 1 fits the register budget",
@@ -884,6 +902,7 @@ sfhk_status sfhk_plan_create(const sfhk_problem* probs, int32_t n_prob,
   P->capacity = ens->capacity;
   P->n_slots = n_slots;
   P->grid = (uint32_t)cus * (uint32_t)t.waves_per_cu;
+  P->grid_latency = (uint32_t)cus * 8;  // two wavefronts per SIMD
   P->accum = accum;
   P->v = v;
   P->Vre = V_re;

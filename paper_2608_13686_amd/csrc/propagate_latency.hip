@@ -1,0 +1,351 @@
+// FP64 trajectory kernel for launches far below device fill (latency form):
+// one trajectory per group of 8 lanes, 8 trajectories per wavefront.
+//
+// Lane c of a group holds column c of the 6x6 monodromy matrix (c < 6; lanes
+// 6 and 7 hold a zero column, which the linear update keeps at zero) and
+// advances it by classical RK4 with the stage Hessians of the trajectory,
+// stage by stage beside the (q, p, S) stages.  Every lane of the group steps
+// (q, p, S) and evaluates the potential itself, so no lane waits for another
+// within a step.  Column c of the doubled HK matrix 2R needs columns c and
+// c + 3 of M: lane c (< 3) reads column c + 3 from lane c + 3, and lane 0
+// gathers the other two columns of 2R from lanes 1 and 2 (DPP row shifts
+// inside the group's row of 16 lanes); lane 0 then takes det R, continues
+// the root C, evaluates the recombination amplitude and deposits.
+//
+// The per-step work on the critical path is the potential and the (q, p, S)
+// stages plus one column's RK4 (84 operations instead of the 6x6 step
+// matrix's ~370), so a step of a trajectory takes about two thirds of the
+// time of the one-trajectory-per-lane kernel, at eight times the lanes per
+// trajectory: the form for a few hundred packs on 1,024 SIMDs (the FP64
+// re-run of trajectories the mixed kernel hands over, small workloads).
+#include "device_common.h"
+
+namespace sfhk {
+namespace {
+
+constexpr int kGroup = 8;                    // lanes per trajectory
+constexpr int kPerWave = kWave / kGroup;     // trajectories per wavefront
+
+// x of lane (lane + N) in the same row of 16 lanes (DPP row shift; lanes
+// whose source is outside the row read 0).  The callers only use lanes
+// whose source lies in their own 8-lane group, which never crosses a row.
+template <int N>
+__device__ __forceinline__ double from_lane_plus(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0x100 + N, 0xf,
+                                                            0xf, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32),
+                                                            0x100 + N, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// maximum over the 8 lanes of the group (3 butterfly levels)
+__device__ __forceinline__ double group_max(double x) {
+  x = fmax(x, __shfl_xor(x, 1, kWave));
+  x = fmax(x, __shfl_xor(x, 2, kWave));
+  return fmax(x, __shfl_xor(x, 4, kWave));
+}
+
+// -K x for the symmetric Hessian K (xx, yy, zz, xy, xz, yz)
+__device__ __forceinline__ void neg_hess_times(const double K[6], const double x[3],
+                                               double out[3]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    out[r] = -(K[sym_idx(r, 0)] * x[0] + K[sym_idx(r, 1)] * x[1] + K[sym_idx(r, 2)] * x[2]);
+}
+
+// One group's record (SFHK_FS_* layout): lane c < 6 writes column c of M,
+// lane 0 the rest.  mmax is the group's running maximum (all lanes).
+__device__ __forceinline__ void write_group_record(double* __restrict__ f, uint64_t st, int c,
+                                                   const double q[3], const double p[3],
+                                                   const double x[3], const double v[3],
+                                                   double S, double Cre, double Cim,
+                                                   double flips, double mmax, double n_near) {
+  if (c < 6) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      f[(SFHK_FS_M + 6 * r + c) * st] = x[r];
+      f[(SFHK_FS_M + 18 + 6 * r + c) * st] = v[r];
+    }
+  }
+  if (c == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      f[(SFHK_FS_Q + a) * st] = q[a];
+      f[(SFHK_FS_P + a) * st] = p[a];
+    }
+    f[SFHK_FS_S * st] = S;
+    f[SFHK_FS_CRE * st] = Cre;
+    f[SFHK_FS_CIM * st] = Cim;
+    f[SFHK_FS_FLIPS * st] = flips;
+    f[SFHK_FS_MMAX * st] = mmax;
+    f[SFHK_FS_NEAR * st] = n_near;
+  }
+}
+
+// The trajectories of one unit (8 consecutive positions of a 64-lane pack):
+// group g of the wavefront takes position unit_pos + g of its problem.
+template <bool Track>
+__device__ __forceinline__ void run_unit(const Desc* __restrict__ descs,
+                                         const double* __restrict__ field, const EnsPtrs& e,
+                                         const int32_t* __restrict__ dep_from,
+                                         double* __restrict__ accum, const Records& rec,
+                                         int prob, uint32_t unit_pos, int lane) {
+  const Desc& d = descs[prob];
+  const int N = d.N;
+  const int c = lane & (kGroup - 1);
+  const uint32_t pos = unit_pos + (uint32_t)(lane / kGroup);
+  const bool valid = pos < e.live_count[prob];
+  const uint32_t slot = valid ? e.order[e.live_start[prob] + pos] : 0u;
+
+  const int k0 = valid ? e.k0[slot] : N + 1;
+  const int kdep = (dep_from != nullptr && valid) ? dep_from[slot] : 0;
+  double q[3] = {e.qx[slot], e.qy[slot], e.qz[slot]};
+  double p[3] = {e.px[slot], e.py[slot], e.pz[slot]};
+  const double n[3] = {e.nx[slot], e.ny[slot], e.nz[slot]};
+  const double w = e.w[slot];
+  const double t0 = d.t_first + (double)k0 * d.dt;
+  const double p0q0 = p[0] * q[0] + p[1] * q[1] + p[2] * q[2] + e.dph[slot];
+  double S = 0.0;
+  // this lane's monodromy column: d(q, p)/dz_c, M(t0) = identity
+  double x[3], v[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    x[r] = (c == r) ? 1.0 : 0.0;
+    v[r] = (c == r + 3) ? 1.0 : 0.0;
+  }
+  double Cre = 1.0, Cim = 0.0, flips = 0.0;
+  const double h = d.dt, hh = 0.5 * d.dt, h6 = d.dt / 6.0;
+  const double* __restrict__ fe = field + d.field_off;
+  double* __restrict__ acc = accum + d.acc_off;
+  // the wavefront's first trajectory is born first (sorted by birth step)
+  const int kmin = __builtin_amdgcn_readfirstlane(k0);
+  double acc_reg = 0.0;
+  int kend = N + 1;  // first step without contribution (prefactor cap)
+  double mmax = 1.0, n_near = 0.0;  // Track only: this lane's column, then the group's
+  int snap_k = Track && rec.snap ? first_snap_step(kmin, rec.snap_every) : -1;
+  const int snap_end = Track && rec.snap ? rec.n_snap * rec.snap_every : 0;
+  const double hRn[3] = {d.half_R * n[0], d.half_R * n[1], d.half_R * n[2]};
+  const double gamma = d.gamma, inv_gamma = d.inv_gamma;
+  // the screening exponential's constants in VGPRs: a lone wavefront would
+  // otherwise wait on a scalar move and its hazard before every Horner step
+  const ExpK ekv = make_expk();
+
+  for (int k = kmin; k <= N; ++k) {
+    bool live = k >= k0 && k < kend;
+    // column c of 2R = Mqq + Mpp - i g Mqp + (i/g) Mpq from columns c, c + 3
+    double x3[3], v3[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      x3[r] = from_lane_plus<3>(x[r]);
+      v3[r] = from_lane_plus<3>(v[r]);
+    }
+    double rr[3], ri[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      rr[r] = x[r] + v3[r];
+      ri[r] = fma(inv_gamma, v[r], -gamma * x3[r]);
+    }
+    double Rr[3][3], Ri[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      Rr[r][0] = rr[r];
+      Ri[r][0] = ri[r];
+      Rr[r][1] = from_lane_plus<1>(rr[r]);
+      Ri[r][1] = from_lane_plus<1>(ri[r]);
+      Rr[r][2] = from_lane_plus<2>(rr[r]);
+      Ri[r][2] = from_lane_plus<2>(ri[r]);
+    }
+    double re_a = 0.0;
+    Geom<double> Gk;  // geometry at q_k: amplitude and first RK4 stage
+    geometry(d, hRn, q, Gk);
+    if (live && c == 0) {
+      prefactor_step(Rr, Ri, Cre, Cim, flips);
+      if (d.c_max2 > 0.0 && Cre * Cre + Cim * Cim > d.c_max2) {
+        kend = k;
+      } else if (k >= kdep) {
+        bool near;
+        re_a = amplitude_re(d, n, p, Gk, Cre, Cim, S, d.t_first + (double)k * h, t0, p0q0, w,
+                            near);
+        if constexpr (Track) n_near += near ? 1.0 : 0.0;
+      }
+    }
+    if (d.c_max2 > 0.0) {  // the cap decision of lane 0 holds for its whole group
+      kend = __shfl(kend, lane & ~(kGroup - 1), kWave);
+      live = k >= k0 && k < kend;
+    }
+    if constexpr (Track) {
+      if (k == snap_k && k < snap_end) {  // wave-uniform
+        const double gm = group_max(mmax);
+        if (valid && k >= k0 && k <= kend)
+          write_group_record(rec.snap + (uint64_t)(k / rec.snap_every) * SFHK_FS_COUNT *
+                                            rec.capacity + slot,
+                             rec.capacity, c, q, p, x, v, S, Cre, Cim, flips, gm, n_near);
+        snap_k += rec.snap_every;
+      }
+    }
+    deposit(re_a, k, N, lane, acc_reg, acc);
+    if (k >= N || !live) continue;
+
+    // --- classical RK4 step t_k -> t_{k+1} of (q, p, S) and of this column
+    const double Ek = fe[2 * k], Eh = fe[2 * k + 1], E1 = fe[2 * k + 2];
+    double K[6], V, g[3];
+    double sq[3], sp3[3], sS, yq[3], yp[3];
+    double sx[3], sv[3], xs[3], vs[3], kv[3];
+
+    potential(d, Gk, V, g, K, &ekv);
+    {
+      const double kp[3] = {-g[0], -g[1], -g[2] - Ek};
+      sS = 0.5 * (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]) - V - q[2] * Ek;
+      neg_hess_times(K, x, kv);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        sq[a] = p[a];
+        sp3[a] = kp[a];
+        yq[a] = q[a] + hh * p[a];
+        yp[a] = p[a] + hh * kp[a];
+        sx[a] = v[a];
+        sv[a] = kv[a];
+        xs[a] = x[a] + hh * v[a];
+        vs[a] = v[a] + hh * kv[a];
+      }
+    }
+    potential(d, hRn, yq, V, g, K, &ekv);
+    {
+      const double kp[3] = {-g[0], -g[1], -g[2] - Eh};
+      sS += 2.0 * (0.5 * (yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]) - V - yq[2] * Eh);
+      neg_hess_times(K, xs, kv);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double kq = yp[a], kx = vs[a];
+        sq[a] += 2.0 * kq;
+        sp3[a] += 2.0 * kp[a];
+        yq[a] = q[a] + hh * kq;
+        yp[a] = p[a] + hh * kp[a];
+        sx[a] += 2.0 * kx;
+        sv[a] += 2.0 * kv[a];
+        xs[a] = x[a] + hh * kx;
+        vs[a] = v[a] + hh * kv[a];
+      }
+    }
+    potential(d, hRn, yq, V, g, K, &ekv);
+    {
+      const double kp[3] = {-g[0], -g[1], -g[2] - Eh};
+      sS += 2.0 * (0.5 * (yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]) - V - yq[2] * Eh);
+      neg_hess_times(K, xs, kv);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double kq = yp[a], kx = vs[a];
+        sq[a] += 2.0 * kq;
+        sp3[a] += 2.0 * kp[a];
+        yq[a] = q[a] + h * kq;
+        yp[a] = p[a] + h * kp[a];
+        sx[a] += 2.0 * kx;
+        sv[a] += 2.0 * kv[a];
+        xs[a] = x[a] + h * kx;
+        vs[a] = v[a] + h * kv[a];
+      }
+    }
+    potential(d, hRn, yq, V, g, K, &ekv);
+    {
+      const double kp[3] = {-g[0], -g[1], -g[2] - E1};
+      sS += 0.5 * (yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]) - V - yq[2] * E1;
+      neg_hess_times(K, xs, kv);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        sq[a] += yp[a];
+        sp3[a] += kp[a];
+        q[a] = q[a] + h6 * sq[a];
+        p[a] = p[a] + h6 * sp3[a];
+        sx[a] += vs[a];
+        sv[a] += kv[a];
+        x[a] = x[a] + h6 * sx[a];
+        v[a] = v[a] + h6 * sv[a];
+      }
+      S = S + h6 * sS;
+    }
+    if constexpr (Track) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) mmax = fmax(mmax, fmax(fabs(x[r]), fabs(v[r])));
+    }
+  }
+
+  if constexpr (Track) {
+    const double gm = group_max(mmax);
+    if (rec.final_state != nullptr && valid)
+      write_group_record(rec.final_state + slot, rec.capacity, c, q, p, x, v, S, Cre, Cim, flips,
+                         gm, n_near);
+  }
+}
+
+// Unit u of the launch: pack u / 8, positions 8 (u % 8) .. + 7 of it.
+__device__ __forceinline__ bool find_unit(const EnsPtrs& e, int n_prob, uint32_t pack,
+                                          uint32_t sub, int& prob, uint32_t& unit_pos) {
+  if (pack >= e.pack_start[n_prob]) return false;
+  int lo = 0, hi = n_prob;  // pack_start[lo] <= pack < pack_start[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (e.pack_start[mid] <= pack) lo = mid; else hi = mid;
+  }
+  prob = lo;
+  unit_pos = (pack - e.pack_start[lo]) * kWave + sub * kPerWave;
+  return unit_pos < e.live_count[lo];
+}
+
+template <bool Track>
+__global__ void __launch_bounds__(kWave)
+propagate_latency_kernel(const Desc* __restrict__ descs, int n_prob,
+                         const double* __restrict__ field, EnsPtrs e,
+                         const int32_t* __restrict__ dep_from, double* __restrict__ accum,
+                         Records rec) {
+  int prob;
+  uint32_t unit_pos;
+  if (!find_unit(e, n_prob, blockIdx.x / kPerWave, blockIdx.x % kPerWave, prob, unit_pos)) return;
+  run_unit<Track>(descs, field, e, dep_from, accum, rec, prob, unit_pos, threadIdx.x);
+}
+
+// Persistent form: a fixed grid pulls units (pack queue[u / 8], positions
+// 8 (u % 8) ..) through an atomic counter until all 8 x (packs) units are
+// taken; every wavefront exits then.
+__global__ void __launch_bounds__(kWave)
+propagate_latency_persistent(const Desc* __restrict__ descs, int n_prob,
+                             const double* __restrict__ field, EnsPtrs e,
+                             const int32_t* __restrict__ dep_from, double* __restrict__ accum,
+                             const uint32_t* __restrict__ queue, uint32_t* __restrict__ counter) {
+  const int lane = threadIdx.x;
+  const uint32_t total = e.pack_start[n_prob] * (uint32_t)kPerWave;
+  for (;;) {
+    uint32_t u = 0;
+    if (lane == 0) u = atomicAdd(counter, 1u);
+    u = __builtin_amdgcn_readfirstlane(u);
+    if (u >= total) break;
+    int prob;
+    uint32_t unit_pos;
+    if (!find_unit(e, n_prob, queue[u / kPerWave], u % kPerWave, prob, unit_pos)) continue;
+    run_unit<false>(descs, field, e, dep_from, accum, Records{}, prob, unit_pos, lane);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_propagate_latency(const Desc* descs, int n_prob, const double* field,
+                                    EnsPtrs e, const int32_t* dep_from, uint32_t max_packs,
+                                    double* accum, const Records& rec, hipStream_t s,
+                                    const LaunchCfg& cfg) {
+  if (max_packs == 0) return hipSuccess;
+  if (cfg.persistent && !rec.any()) {
+    hipLaunchKernelGGL(propagate_latency_persistent, dim3(cfg.grid), dim3(kWave), 0, s, descs,
+                       n_prob, field, e, dep_from, accum, cfg.queue, cfg.counter);
+  } else {
+    const dim3 grid((uint32_t)((uint64_t)max_packs * kPerWave));
+    if (rec.any())
+      hipLaunchKernelGGL(propagate_latency_kernel<true>, grid, dim3(kWave), 0, s, descs, n_prob,
+                         field, e, dep_from, accum, rec);
+    else
+      hipLaunchKernelGGL(propagate_latency_kernel<false>, grid, dim3(kWave), 0, s, descs, n_prob,
+                         field, e, dep_from, accum, rec);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace sfhk

@@ -163,6 +163,17 @@ struct Records {
 hipError_t launch_propagate_f64(const Desc* descs, int n_prob, const double* field, EnsPtrs e,
                                 const int32_t* dep_from, uint32_t max_packs, double* accum,
                                 const Records& rec, hipStream_t s, const LaunchCfg& cfg);
+// The same FP64 propagation with one trajectory per 8-lane group (latency
+// form, propagate_latency.hip): grid 8 max_packs, or with cfg.persistent a
+// grid of cfg.grid wavefronts pulling 8-trajectory units of the packs in
+// cfg.queue (records need the per-pack grid).
+hipError_t launch_propagate_latency(const Desc* descs, int n_prob, const double* field,
+                                    EnsPtrs e, const int32_t* dep_from, uint32_t max_packs,
+                                    double* accum, const Records& rec, hipStream_t s,
+                                    const LaunchCfg& cfg);
+// Largest pack count an automatic choice runs in the latency form: eight
+// wavefronts per pack, at most one per SIMD of a 256-CU device.
+constexpr uint32_t kLatencyMaxPacks = 128;
 // redo (per slot, preset to -1): set to the first step left to the FP64 re-run.
 hipError_t launch_propagate_mixed(const Desc* descs, int n_prob, const double* field, EnsPtrs e,
                                   int32_t* redo, uint32_t max_packs, double* accum,
