@@ -170,6 +170,12 @@ Desc make_desc(const sfhk_problem& p) {
   d.kcube3 = d.kappa * d.kappa * d.kappa / 3.0;
   d.inv_E0 = E0 > 0 ? 1.0 / E0 : 0.0;
   d.c_max2 = p.c_max > 0.0 ? p.c_max * p.c_max : 0.0;
+  {
+    const double h = p.dt;
+    d.rk = {h, 0.5 * h, h / 6.0, h * h / 6.0, h * h * h / 12.0, h * h * h * h / 24.0};
+    const float f = (float)p.dt;
+    d.frk = {f, 0.5f * f, f / 6.0f, f * f / 6.0f, f * f * f / 12.0f, f * f * f * f / 24.0f};
+  }
   d.nfix[0] = std::sin(p.al.theta) * std::cos(p.al.phi);
   d.nfix[1] = std::sin(p.al.theta) * std::sin(p.al.phi);
   d.nfix[2] = std::cos(p.al.theta);

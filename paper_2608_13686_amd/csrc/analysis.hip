@@ -82,8 +82,8 @@ __global__ void __launch_bounds__(kWave) returns_kernel(const Desc* __restrict__
     for (int a = 0; a < 3; ++a) {
       sq[a] += yp[a];
       sp[a] += -g[a] - (a == 2 ? E1 : 0.0);
-      q[a] = q[a] + (h / 6.0) * sq[a];
-      p[a] = p[a] + (h / 6.0) * sp[a];
+      q[a] = q[a] + d.rk.h6 * sq[a];
+      p[a] = p[a] + d.rk.h6 * sp[a];
     }
   }
   if (pk.valid) {

@@ -377,8 +377,9 @@ struct StepMatrix {
 // O(h^2 K) parts keep full relative precision in FP32.
 template <typename T, bool Inc = false>
 __device__ __forceinline__ void rk4_step_matrix(const T K1[6], const T K2[6], const T K3[6],
-                                                const T K4[6], T h, StepMatrix<T>& P) {
-  const T c2 = h * h / T(6), c3 = h * h * h / T(12), c4 = h * h * h * h / T(24), c1 = h / T(6);
+                                                const T K4[6], const RkCoef<T>& rk,
+                                                StepMatrix<T>& P) {
+  const T h = rk.h, c2 = rk.c2, c3 = rk.c3, c4 = rk.c4, c1 = rk.h6;
   T s23[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) s23[i] = K2[i] + K3[i];

@@ -164,17 +164,17 @@ __device__ __forceinline__ void run_pack(const Desc* __restrict__ descs,
       for (int a = 0; a < 3; ++a) {
         sq[a] += yp[a];
         sp3[a] += kp[a];
-        q[a] = q[a] + (h / 6.0) * sq[a];
-        p[a] = p[a] + (h / 6.0) * sp3[a];
+        q[a] = q[a] + d.rk.h6 * sq[a];
+        p[a] = p[a] + d.rk.h6 * sp3[a];
       }
       sS += kS;
-      S = S + (h / 6.0) * sS;
+      S = S + d.rk.h6 * sS;
     }
     // monodromy: M <- P M with the RK4 step matrix of the stage Hessians
     // K1..K4 of this step (the exact Jacobian of the discrete RK4 map);
     // columns c and c + 3 give column c of R.
     StepMatrix<double> P;
-    rk4_step_matrix(K1, K2, K3, K4, h, P);
+    rk4_step_matrix(K1, K2, K3, K4, d.rk, P);
     monodromy_step<kWave, Track>(P, mono, lane, d.gamma, d.inv_gamma, Rr, Ri, &mmax);
   }
   }

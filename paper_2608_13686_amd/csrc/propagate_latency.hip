@@ -115,7 +115,7 @@ __device__ __forceinline__ void run_unit(const Desc* __restrict__ descs,
     v[r] = (c == r + 3) ? 1.0 : 0.0;
   }
   double Cre = 1.0, Cim = 0.0, flips = 0.0;
-  const double h = d.dt, hh = 0.5 * d.dt, h6 = d.dt / 6.0;
+  const double h = d.rk.h, hh = d.rk.hh, h6 = d.rk.h6;
   const double* __restrict__ fe = field + d.field_off;
   double* __restrict__ acc = accum + d.acc_off;
   // the wavefront's first trajectory is born first (sorted by birth step)

@@ -79,8 +79,7 @@ __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
   double Cre = 1.0, Cim = 0.0, flips = 0.0;
 
   const double hd = d.dt;
-  const float h = (float)d.dt;
-  const float hh = 0.5f * h, h6 = h / 6.0f;
+  const float h = d.frk.h, hh = d.frk.hh, h6 = d.frk.h6;
   const double* __restrict__ fe = field + d.field_off;
   double* __restrict__ acc = accum + d.acc_off;
   const int kmin = __builtin_amdgcn_readfirstlane(k0);
@@ -201,12 +200,12 @@ __device__ __forceinline__ void run_pack_mixed(const Desc* __restrict__ descs,
         q[a] = q[a] + h6 * sq[a];
         p[a] = p[a] + h6 * sp3[a];
       }
-      S = S + (hd / 6.0) * (double)sS;
+      S = S + d.rk.h6 * (double)sS;
     }
     // monodromy: M <- M + (P - I) M with the RK4 step matrix of K1..K4,
     // its identity part left out so that FP32 keeps the O(h^2 K) terms
     StepMatrix<float> P;
-    rk4_step_matrix<float, true>(K1, K2, K3, K4, h, P);
+    rk4_step_matrix<float, true>(K1, K2, K3, K4, d.frk, P);
     const float mmax = monodromy_step_f32(P, mono, lane);
     if constexpr (Track) mmax_all = fmaxf(mmax_all, mmax);
     // FP32 rounding is amplified by the monodromy matrix: past the bound the

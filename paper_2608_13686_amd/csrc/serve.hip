@@ -165,14 +165,14 @@ serve_slice_f64(const ReqDev* __restrict__ reqs, SliceTable tab) {
       for (int a = 0; a < 3; ++a) {
         sq[a] += yp[a];
         sp3[a] += kp[a];
-        q[a] = q[a] + (h / 6.0) * sq[a];
-        p[a] = p[a] + (h / 6.0) * sp3[a];
+        q[a] = q[a] + d.rk.h6 * sq[a];
+        p[a] = p[a] + d.rk.h6 * sp3[a];
       }
       sS += kS;
-      S = S + (h / 6.0) * sS;
+      S = S + d.rk.h6 * sS;
     }
     StepMatrix<double> P;
-    rk4_step_matrix(K1, K2, K3, K4, h, P);
+    rk4_step_matrix(K1, K2, K3, K4, d.rk, P);
     monodromy_step(P, mono, lane, d.gamma, d.inv_gamma, Rr, Ri);
   }
   // flush the partial 64-step block of dipole sums left at the window end

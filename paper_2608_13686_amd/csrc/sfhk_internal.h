@@ -12,6 +12,15 @@ namespace sfhk {
 constexpr int kWave = 64;
 constexpr double kPi = 3.14159265358979323846;
 
+// Coefficients of one RK4 step of length h: h/2, h/6 and the step matrix's
+// h^2/6, h^3/12, h^4/24.  Computed on the host (FP64, and from the FP32 h in
+// FP32) with the same operations a kernel would use: a division in a step
+// loop costs about ten VALU instructions.
+template <typename T>
+struct RkCoef {
+  T h, hh, h6, c2, c3, c4;
+};
+
 // Per-problem constants, derived once on the host and read by every kernel
 // through wave-uniform (scalar) loads.
 struct Desc {
@@ -49,7 +58,17 @@ struct Desc {
   double sh_ns[SFHK_MAX_GTO], sh_np[SFHK_MAX_GTO];
   double g_inv4k_min;  // smallest 1/(4 kappa2) over the shells
   double c_max2;       // prefactor cap squared (0: none)
+  RkCoef<double> rk;   // RK4 coefficients of h = dt
+  RkCoef<float> frk;   // the same for the FP32 h = (float) dt
 };
+
+template <typename T> __host__ __device__ inline const RkCoef<T>& rk_coef(const Desc& d);
+template <> __host__ __device__ inline const RkCoef<double>& rk_coef<double>(const Desc& d) {
+  return d.rk;
+}
+template <> __host__ __device__ inline const RkCoef<float>& rk_coef<float>(const Desc& d) {
+  return d.frk;
+}
 
 // True if any problem is born by the saddle-point step (it selects the
 // sampler with that code).
