@@ -120,3 +120,21 @@ def test_sincos_error_below_stated_bound():
         xm = mp.mpf(float(x))
         worst = max(worst, float(abs(s - mp.sin(xm))), float(abs(c - mp.cos(xm))))
     assert worst < 2.0 ** -52, worst
+
+
+def test_constants_are_the_committed_generator_output():
+    """Every polynomial and reduction constant of the device exponential and
+    sine/cosine is what csrc/fit_device_math.py computes (Chebyshev fits in
+    40-digit arithmetic, rounded to double)."""
+    import importlib.util
+    path = os.path.join(os.path.dirname(SRC), "fit_device_math.py")
+    spec = importlib.util.spec_from_file_location("fit_device_math", path)
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    want = gen.fits()
+    assert exp_constants() == want["exp"]
+    assert constants("exp_neg2") == want["exp"]
+    text = open(SRC).read()
+    m = re.search(r"const double v\[13\] = \{(.*?)\};", text, re.S)
+    assert [float(x) for x in m.group(1).replace("\n", " ").split(",")] == want["exp"]
+    assert sincos_constants() == want["sincos"]
