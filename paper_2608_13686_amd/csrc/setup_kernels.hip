@@ -233,20 +233,86 @@ __global__ void scatter_kernel(const Desc* __restrict__ descs, uint64_t n_slots,
 }
 
 // Within each bin the scatter order is arbitrary; sort every bin's slots
-// ascending so that the pack layout is deterministic.
-__global__ void sort_bins_kernel(const uint32_t* __restrict__ start, uint64_t n_bins,
-                                 uint32_t* __restrict__ order) {
-  uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n_bins) return;
-  uint32_t lo = start[b], hi = start[b + 1];
-  for (uint32_t i = lo + 1; i < hi; ++i) {
-    uint32_t v = order[i];
-    uint32_t j = i;
-    while (j > lo && order[j - 1] > v) {
-      order[j] = order[j - 1];
-      --j;
+// ascending so that the pack layout is deterministic.  The bitonic network in
+// its all-ascending form (the first step of each merge compares mirror
+// images) puts the smaller value at the lower index in every compare-exchange,
+// so entries past a bin's end act as +infinity and their exchanges are
+// skipped, with no padding: O(n log^2 n) work per bin at any occupancy.
+// Each thread of a block owns one bin; the block's waves take its bins of
+// 2..kSortWave entries one at a time, each sorted by one wave in its own LDS
+// region (LDS operations of a wave complete in issue order, so a compiler
+// fence between steps suffices); larger bins are then sorted one after the
+// other by the whole block in place in global memory, a barrier between
+// steps.
+constexpr uint32_t kSortWave = 2048;
+
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sorts a[0, n) by the threads t0, t0 + stride, ... of the group that calls
+// it; sync() separates the steps.
+template <typename Sync>
+__device__ void bitonic_sort(uint32_t* a, uint64_t n, uint32_t t0, uint32_t stride, Sync sync) {
+  uint64_t m = 1;
+  while (m < n) m <<= 1;
+  for (uint64_t k = 2; k <= m; k <<= 1) {
+    for (uint64_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint64_t t = t0; t < m / 2; t += stride) {
+        // the t-th index with bit j clear, and its partner above it
+        const uint64_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+        const uint64_t l = j == k >> 1 ? i ^ (k - 1) : i + j;
+        if (l < n) {
+          const uint32_t x = a[i], y = a[l];
+          if (x > y) {
+            a[i] = y;
+            a[l] = x;
+          }
+        }
+      }
+      sync();
     }
-    order[j] = v;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) sort_bins_kernel(const uint32_t* __restrict__ start,
+                                                           uint64_t n_bins, uint32_t* order) {
+  __shared__ uint32_t buf[kBlock / kWave][kSortWave];
+  __shared__ uint32_t big_lo[kBlock], big_n[kBlock];
+  __shared__ uint32_t n_big;
+  const uint32_t lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  if (threadIdx.x == 0) n_big = 0;
+  __syncthreads();
+  const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t lo = 0, n = 0;
+  if (b < n_bins) {
+    lo = start[b];
+    n = start[b + 1] - lo;
+  }
+  if (n > kSortWave) {
+    const uint32_t at = atomicAdd(&n_big, 1u);
+    big_lo[at] = lo;
+    big_n[at] = n;
+  }
+  uint64_t todo = __ballot(n >= 2 && n <= kSortWave);
+  uint32_t* a = buf[wave];
+  while (todo) {
+    const int src = __ffsll((unsigned long long)todo) - 1;
+    todo &= todo - 1;
+    const uint32_t blo = __shfl(lo, src), bn = __shfl(n, src);
+    for (uint32_t t = lane; t < bn; t += kWave) a[t] = order[blo + t];
+    wave_fence();
+    bitonic_sort(a, bn, lane, kWave, wave_fence);
+    for (uint32_t t = lane; t < bn; t += kWave) order[blo + t] = a[t];
+    wave_fence();
+  }
+  __syncthreads();
+  const uint32_t nb = n_big;
+  for (uint32_t k = 0; k < nb; ++k) {
+    const uint32_t blo = big_lo[k], bn = big_n[k];
+    bitonic_sort(order + blo, bn, threadIdx.x, kBlock, [] { __syncthreads(); });
   }
 }
 
@@ -523,7 +589,8 @@ hipError_t launch_sort(const Desc* descs, int n_prob, uint64_t n_slots, uint64_t
   if (n_slots > 0)
     hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(n_slots, kBlock)), dim3(kBlock), 0, s,
                        descs, n_slots, cursor, e, select, out.order);
-  hipLaunchKernelGGL(sort_bins_kernel, dim3(blocks_for(n_bins, kBlock)), dim3(kBlock), 0, s, hist,
+  if (n_bins > 0)
+    hipLaunchKernelGGL(sort_bins_kernel, dim3(blocks_for(n_bins, kBlock)), dim3(kBlock), 0, s, hist,
                      n_bins, out.order);
   return hipGetLastError();
 }

@@ -109,6 +109,25 @@ def test_sampling_matches_oracle(sf, orc, case):
     assert np.array_equal(g["pack_start"], np.concatenate([[0], np.cumsum(packs)]))
 
 
+def test_pack_order_with_crowded_bins(sf):
+    """The per-bin sort at any bin occupancy: a coarse time step crowds
+    thousands of births into each step of the field peaks (bins above the
+    2048 entries one wave sorts in LDS, sorted by a whole block in global
+    memory), beside a problem of sparse bins; the order is the stable
+    (problem, k0, slot) order, bit-exact."""
+    coarse = workloads.with_changes(workloads.h2_softcore(), dt=4.0)
+    probs, n, seeds = [coarse, workloads.n2(0.0)], [400000, 20000], [11, 12]
+    ens, _ = gpu_sample(sf, probs, n, seeds)
+    g = ens_host(ens)
+    live = np.nonzero(g["w"][:sum(n)] > 0)[0]
+    counts = np.bincount(g["k0"][live][g["prob"][live] == 0])
+    print(f"largest bin {counts.max()}, bins over 2048: {(counts > 2048).sum()}, "
+          f"2..2048: {((counts >= 2) & (counts <= 2048)).sum()}", flush=True)
+    assert counts.max() > 2 * 2048
+    want = live[np.lexsort((live, g["k0"][live], g["prob"][live]))]
+    assert np.array_equal(g["order"][:live.size], want)
+
+
 # ---------------------------------------------------------- trajectories
 def check_final_states(sf, orc, probs, n, seeds, picks_per_problem=12, seed=0):
     import torch
