@@ -14,7 +14,9 @@
  * Conventions
  *  - Atomic units, except the laser (nm, W/cm^2, optical cycles, rad).
  *  - Every pointer documented as "device" is a HIP device pointer owned by
- *    the caller; the library never allocates or frees device memory.
+ *    the caller; the library never allocates or frees device memory (apart
+ *    from the one fixed array behind sfhk_propagate_static, reserved when
+ *    the library is loaded on a GPU).
  *    "host" pointers are read during the call only.
  *  - `stream` is a hipStream_t (NULL = the null stream).  All device work is
  *    enqueued asynchronously on it; outputs are valid once it completes.
@@ -228,10 +230,10 @@ sfhk_status sfhk_sample_initial(const sfhk_problem* probs, int32_t n_prob,
  *          n_snap >= 1 and snap_every >= 1 when snapshots is non-null.
  *          Asking for either record runs the one-wavefront-per-pack kernel
  *          that keeps them (same arithmetic as without).
- *   Launches of at most 128 64-lane packs (capacity <= 128 x 64 - n_prob
- *   slots) run one trajectory per 8 lanes (latency form: same equations,
- *   RK4 applied per monodromy column instead of through the RK4 step
- *   matrix), and so does the FP64 re-run of the mixed form.
+ *   An FP64 launch of at most 128 64-lane packs (ceil(capacity / 64) +
+ *   n_prob <= 128) runs one trajectory per 8 lanes (latency form: same
+ *   equations, RK4 applied per monodromy column instead of through the RK4
+ *   step matrix), and so does the FP64 re-run of the mixed form.
  *   precision: SFHK_FP64 (everything FP64) or SFHK_MIXED: q, p, the
  *          potential and its derivatives, the monodromy matrix and det R in
  *          FP32; S, the root of det R with its branch, the amplitude and the
@@ -323,10 +325,12 @@ typedef struct {
                             1: a persistent grid pulls packs, longest first, from a device queue */
   int32_t waves_per_cu;  /* persistent grid = 256 CUs x waves_per_cu wavefronts, 1..32 (0: 8) */
   int32_t step_unroll;   /* RK4 steps per loop trip: 1, 2 or 4 (0: 1) */
-  int32_t traj_per_lane; /* trajectories per lane: 1 (0: 1).  The FP64 state of one
-                            trajectory fills the register budget of two wavefronts per SIMD;
-                            two FP32 trajectories per lane would pay only through packed FP32
-                            arithmetic, which this build does not emit */
+  int32_t traj_per_lane; /* trajectories per lane: 1 (0: 1).  FP64: the state of one
+                            trajectory fills the register budget of two wavefronts per SIMD.
+                            Mixed: two FP32 trajectories per lane would pay only through
+                            packed FP32 arithmetic (two lanes' worth per instruction), which
+                            the library does not emit: some packed-FP32 forms have given
+                            silently wrong results now and then */
   int32_t lanes_per_traj; /* lanes per trajectory of the FP64 re-run of trajectories the mixed
                             form hands over: 1, or 8 for the latency form (one monodromy column
                             per lane); 0: 8 */
@@ -427,6 +431,17 @@ sfhk_status sfhk_request_init(const sfhk_problem* p, uint64_t n_traj, uint64_t s
 sfhk_status sfhk_serve_window(void* table, int32_t table_slots, int32_t n, const int32_t* slots,
                               const uint64_t* n_traj, const int32_t* k_from, const int32_t* k_to,
                               int32_t group, int32_t n_groups, void* stream);
+
+/* Advance one admitted request (slot `slot`, admitted by sfhk_request_init
+ * with the same p, n_traj, n_omega and buffer) over its whole pulse, steps
+ * 0..N, in one launch of the FP64 kernel of sfhk_propagate (one wavefront per
+ * 64-lane pack): the same result as sfhk_serve_window over [0, N+1) for this
+ * request, for a request that runs alone from its first step to its last.
+ * The state kept between windows is not written, so no window may follow;
+ * sfhk_request_finalize comes next.  Sec. II.A; Eq. 4-6. */
+sfhk_status sfhk_request_run(const sfhk_problem* p, uint64_t n_traj, int32_t n_omega,
+                             void* buffer, size_t buffer_bytes, void* table, int32_t table_slots,
+                             int32_t slot, void* stream);
 
 /* Dipole (v = 2 accum / n_traj) and spectrum of a request whose windows have
  * covered steps 0..N; results at sfhk_request_layout's offsets. */

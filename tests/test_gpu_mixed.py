@@ -12,9 +12,11 @@ import workloads
 pytestmark = pytest.mark.gpu
 
 NTHREADS = min(16, os.cpu_count() or 1)
-# stated accuracy of the mixed form on these workloads
-MIXED_REL_L2 = 5e-2
-MIXED_SPECTRAL_DB_MEDIAN = 0.5
+# stated accuracy of the mixed form on these workloads, a few times the
+# measured relative L2 errors (H2 2.4e-5; N2 4.6e-2 at 0 degrees, 5.3e-5 at
+# 90 degrees); the spectra move by a median 0.007 dB (N2) or less.
+MIXED_REL_L2 = {"H2": 1e-4, "N2": 1e-1}
+MIXED_SPECTRAL_DB_MEDIAN = 0.05
 
 
 @pytest.fixture(scope="module")
@@ -65,7 +67,7 @@ def test_mixed_dipole_error_vs_fp64(sf, mol):
         med, p90 = spectral_db(sf, p, v64, vmx, h_lo, h_hi)
         print(f"{p['name']} theta={p['align']['theta']:.3f}: mixed vs FP64 relative L2 {rel:.3e}, "
               f"spectral |dB| median {med:.3f}, 90th pct {p90:.3f} (H{h_lo:g}-H{h_hi:g})")
-        assert rel < MIXED_REL_L2
+        assert rel < MIXED_REL_L2[mol]
         assert med < MIXED_SPECTRAL_DB_MEDIAN
 
 

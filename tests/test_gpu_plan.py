@@ -125,7 +125,9 @@ def test_plan_mixed_error_vs_fp64(sf):
         out[prec] = [plan.v_of(i).cpu().numpy() for i in range(len(probs))]
         plan.close()
     for i in range(len(probs)):
-        assert rel(out["mixed"][i], out["fp64"][i]) < 5e-2
+        e = rel(out["mixed"][i], out["fp64"][i])
+        print(f"problem {i}: mixed plan vs FP64 plan, relative L2 {e:.3e}", flush=True)
+        assert e < 1e-2  # measured 2.5e-5, 8.5e-5 and 1.8e-3
 
 
 def test_batched_workload_full_size(sf, orc):
