@@ -423,25 +423,34 @@ def analysis_variant(sf, probs, ens, ws, v, offs, lens):
     return res
 
 
-def averaging_variant(sf, sizes=(1 << 14, 1 << 16, 1 << 18, 1 << 20), reps=3,
-                      n_ref=1 << 26):
-    """Isotropic H2 two ways at equal trajectory counts (Eq. 5 with ten fixed
-    alignments at Gauss-Legendre nodes in cos(theta), each with N_s/10
-    trajectories, against the joint Monte Carlo over the axis of Eq. 6 with
-    N_s trajectories), both against a joint run with 2^26 trajectories:
-    relative L2 error of the averaged dipole, median |dB| error of the yield
-    at the odd harmonics 5..33 (the plateau below the cutoff), and the
-    trajectory ratio for equal dipole error, (err_standard / err_joint)^2."""
+def averaging_study(sf, mol, ionization, sizes, reps, n_ref, cap=False):
+    """Isotropic average of one molecule two ways at equal trajectory counts
+    (Eq. 5 with ten fixed alignments at Gauss-Legendre nodes in cos(theta),
+    each with N_s/10 trajectories, against the joint Monte Carlo over the
+    axis of Eq. 6 with N_s trajectories), both against a joint run with n_ref
+    trajectories.  ionization: "first_order" (an alignment-independent
+    tunnelling weight) or "saddle" (the weight carries the axis-dependent
+    ionisation matrix element of Eq. 1, the sampling weight of Eq. 6).  cap:
+    every problem with the prefactor cap above free spreading, which cuts the
+    strongly amplifying trajectories.  Per size: relative L2 error of the
+    averaged dipole and median |dB| error of the yield at the odd harmonics
+    5..33, root mean square over `reps` independent runs, and the trajectory
+    ratio for equal dipole error, (err_standard / err_joint)^2."""
     import torch
-    av = workloads.workload_averaging("H2", 10)
+    av = workloads.workload_averaging(mol, 10)
     probs_s, wts = av["standard"]
     joint = av["joint"]
+    probs_s = [workloads.with_changes(p, ionization=ionization) for p in probs_s]
+    joint = workloads.with_changes(joint, ionization=ionization)
+    if cap:
+        probs_s = [dict(p, c_max=chaos_cap(sf, p)) for p in probs_s]
+        joint = dict(joint, c_max=chaos_cap(sf, joint))
     N, t0, tau = sf.problem_steps(joint)
     w0 = 45.56335252912 / joint["laser"]["lambda_nm"]
     om = torch.tensor([h * w0 for h in range(5, 35, 2)], dtype=torch.float64, device="cuda")
 
     def joint_v(n, seed):
-        chunk, acc, done = 1 << 23, None, 0
+        chunk, acc, done = 1 << 22, None, 0
         while done < n:
             m = min(chunk, n - done)
             out = sf.run([joint], [m], [seed], h_max=1.0)
@@ -481,61 +490,90 @@ def averaging_variant(sf, sizes=(1 << 14, 1 << 16, 1 << 18, 1 << 20), reps=3,
                      "odd_harmonic_db_joint": rms(ej, 1), "odd_harmonic_db_standard": rms(es, 1),
                      "trajectory_ratio": (rms(es, 0) / rms(ej, 0)) ** 2})
     torch.cuda.synchronize()
-    return {"workload": "isotropic-h2-averaging", "reference_trajectories": n_ref,
-            "repetitions": reps, "angles": [round(a, 3) for a in av["thetas_deg"]],
-            "rows": rows, "seconds": time.perf_counter() - t}
+    return {"reference_trajectories": n_ref, "repetitions": reps, "rows": rows,
+            "seconds": time.perf_counter() - t}
 
 
-def served_variant(sf, n_req, rates, window=1024, h_max=100.0, h_step=0.1, n_groups=2):
-    """p50/p99 latency and spectra/s of seeded Poisson request streams (one
-    per arrival rate) under continuous batching (processor sharing and
-    shortest-remaining-work) and under a FIFO server on the plain FP64 path.
-    One executor (one pool, one set of streams) serves every stream."""
+def averaging_variant(sf, sizes=(1 << 14, 1 << 16, 1 << 18, 1 << 20), reps=3):
+    """The averaging study for H2 and N2, each with the first-order sampler
+    and with the saddle-point sampler whose weight carries the axis-dependent
+    ionisation element (the Eq. 6 weight), each as sampled and with the
+    strongly amplifying trajectories cut by the prefactor cap (how much of the
+    Monte Carlo error they carry)."""
+    out = {"angles": [round(a, 3) for a in workloads.workload_averaging("H2")["thetas_deg"]]}
+    for mol, n_ref in (("H2", 1 << 26), ("N2", 1 << 25)):
+        for ion in ("first_order", "saddle"):
+            for cap in (False, True):
+                key = f"{mol}-{ion}" + ("-capped" if cap else "")
+                out[key] = averaging_study(sf, mol, ion, sizes, reps if not cap else 2, n_ref,
+                                           cap)
+                print(f"averaging {key}: {out[key]}", file=sys.stderr, flush=True)
+    return out
+
+
+def served_variant(sf, n_req, loads, h_max=100.0, h_step=0.1, n_sat=200):
+    """Latency of a seeded Poisson stream of spectrum requests at fractions of
+    the device's saturation rate, under continuous batching (shortest
+    remaining work first, time-targeted windows) and under a FIFO server that
+    runs one request at a time on the plain FP64 path, both live.
+
+    Saturation: the first n_sat requests of the stream alone on the plain FP64
+    path, back to back; saturation spectra/s = requests / their total time.
+    The stream is drawn once at 1 request/s and its arrival times are scaled
+    to each rate (same requests, same order)."""
     import torch
     from paper_2608_13686_amd.serve import (HipExecutor, Server, fifo_stream, latency_stats,
                                             plain_fp64_runner, serve_stream)
     n_omega = int(round(h_max / h_step)) + 1
+    unit = workloads.request_stream(n_req, 1.0)
+    runner = plain_fp64_runner(h_max, h_step)
+    runner(unit[0][1], 4096, 1)  # warm-up
+    t = time.perf_counter()
+    for _, p, n, seed in unit[:n_sat]:
+        runner(p, n, seed)
+    svc = (time.perf_counter() - t) / min(n_sat, len(unit))
+    sat = 1.0 / svc
+    print(f"saturation {sat:.2f} spectra/s (mean service {1e3 * svc:.1f} ms over {n_sat})",
+          file=sys.stderr, flush=True)
     pool = 48 << 30
-    x = HipExecutor(pool, 64, n_omega, h_step, n_groups=n_groups)
-    # untimed warm-up: one small request through every kernel
-    warm_prob = workloads.request_stream(1, rates[0])[0][1]
-    warm = Server(x, pool, max_requests=64, window=window)
-    warm.submit("warm", warm_prob, 4096, 1)
+    x = HipExecutor(pool, 64, n_omega, h_step)
+    warm = Server(x, pool, max_requests=64)
+    warm.submit("warm", unit[0][1], 4096, 1)
     warm.drain()
-    plain_fp64_runner(h_max, h_step)(warm_prob, 4096, 1)
     torch.cuda.synchronize()
 
-    def summary(done, t_first, wall):
+    def summary(done, t0, wall):
         st = latency_stats(done)
-        span = max(r.finished for r in done) - t_first
+        span = max(r.finished for r in done) - t0
         return {"completed": len(done), "p50_s": st["p50_s"], "p99_s": st["p99_s"],
                 "mean_s": st["mean_s"], "max_s": st["max_s"], "spectra_per_s": len(done) / span,
                 "wall_s": wall}
 
-    out = []
-    for rate_hz in rates:
-        stream = workloads.request_stream(n_req, rate_hz)
-        res = {"workload": f"poisson-{n_req}req-{rate_hz:g}hz-seed1004", "n_requests": n_req,
-               "rate_hz": rate_hz, "window_steps": window, "pack_groups": n_groups,
-               "n_omega": n_omega,
-               "trajectories_total": int(sum(n for _, _, n, _ in stream)),
-               "precision": "fp64"}
-        for policy in ("ps", "srpt"):
-            S = Server(x, pool, max_requests=64, window=window, policy=policy)
-            t = time.perf_counter()
-            done = serve_stream(S, stream)
-            wall = time.perf_counter() - t
-            res[f"served_{policy}"] = summary(done, t, wall)
-            res[f"served_{policy}"]["peak_pool_bytes"] = S.peak_bytes
-            res[f"served_{policy}"]["peak_concurrent"] = S.peak_active
-            print(f"served ({policy}, {rate_hz:g}/s): {res[f'served_{policy}']}", file=sys.stderr,
-                  flush=True)
+    out = {"workload": f"poisson-{n_req}req-seed1004", "n_requests": n_req,
+           "trajectories_total": int(sum(n for _, _, n, _ in unit)), "n_omega": n_omega,
+           "precision": "fp64", "saturation_spectra_per_s": sat,
+           "saturation_from": f"first {n_sat} requests back to back on the plain FP64 path",
+           "served_policy": "srpt by estimated time left less 0.5 x waiting time, launches "
+                            "filled to 8,192 wavefronts, windows of ~40 ms ending with the "
+                            "shortest request of each launch, one window in flight; a request "
+                            "alone runs its whole pulse in one launch of the plain FP64 kernel",
+           "loads": []}
+    for load in loads:
+        rate = load * sat
+        stream = [(t / rate, p, n, seed) for (t, p, n, seed) in unit]
+        S = Server(x, pool, max_requests=64)
         t = time.perf_counter()
-        done = fifo_stream(stream, plain_fp64_runner(h_max, h_step))
-        wall = time.perf_counter() - t
-        res["fifo_fp64"] = summary(done, t, wall)
-        print(f"fifo ({rate_hz:g}/s): {res['fifo_fp64']}", file=sys.stderr, flush=True)
-        out.append(res)
+        done = serve_stream(S, stream)
+        res = {"load": load, "rate_hz": rate,
+               "served_srpt": dict(summary(done, t, time.perf_counter() - t),
+                                   peak_pool_bytes=S.peak_bytes, peak_concurrent=S.peak_active)}
+        print(f"served at {load:g} x saturation ({rate:.2f}/s): {res['served_srpt']}",
+              file=sys.stderr, flush=True)
+        t = time.perf_counter()
+        done = fifo_stream(stream, runner)
+        res["fifo_fp64"] = summary(done, t, time.perf_counter() - t)
+        print(f"fifo at {load:g} x saturation: {res['fifo_fp64']}", file=sys.stderr, flush=True)
+        out["loads"].append(res)
     return out
 
 
@@ -553,9 +591,9 @@ def main():
     ap.add_argument("--only", default="",
                     help="comma list of variants to run (mixed, batched, small, analysis, "
                          "saddle, averaging, served); default all")
-    ap.add_argument("--serve-requests", type=int, default=120)
-    ap.add_argument("--serve-rate", default="12,16",
-                    help="Poisson arrivals per second; a comma list runs one stream per rate")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-loads", default="0.5,0.8",
+                    help="arrival rates as fractions of the measured saturation rate")
     args = ap.parse_args()
     only = {x for x in args.only.split(",") if x}
     unknown = only - {"mixed", "batched", "small", "analysis", "saddle", "averaging", "served"}
@@ -762,9 +800,8 @@ def main():
             print(f"averaging: {variants['averaging']}", file=sys.stderr, flush=True)
             torch.cuda.empty_cache()
         if want("served") and args.serve_requests > 0:
-            rates = [float(r) for r in str(args.serve_rate).split(",") if r]
-            for i, res in enumerate(served_variant(sf, args.serve_requests, rates)):
-                variants["served" if i == 0 else f"served_{rates[i]:g}hz"] = res
+            loads = [float(r) for r in str(args.serve_loads).split(",") if r]
+            variants["served"] = served_variant(sf, args.serve_requests, loads)
         out["variants"] = variants
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["parity"] = cpu_baseline_and_parity(sf, probs, seeds)

@@ -19,7 +19,7 @@ EXPORTS = ["sfhk_abi_version", "sfhk_last_error", "sfhk_problem_steps", "sfhk_wo
            "sfhk_plan_workspace_bytes", "sfhk_plan_create", "sfhk_plan_run", "sfhk_plan_capture",
            "sfhk_plan_replay", "sfhk_plan_destroy", "sfhk_plan_kernel_ms", "sfhk_request_bytes", "sfhk_request_layout",
            "sfhk_request_table_bytes", "sfhk_request_init", "sfhk_serve_window",
-           "sfhk_request_finalize", "sfhk_gabor", "sfhk_return_steps"]
+           "sfhk_request_run", "sfhk_request_finalize", "sfhk_gabor", "sfhk_return_steps"]
 
 
 class Center(C.Structure):
@@ -139,6 +139,9 @@ def lib():
         L.sfhk_serve_window.argtypes = [C.c_void_p, C.c_int32, C.c_int32, i32p, u64p, i32p,
                                         i32p, C.c_int32, C.c_int32, C.c_void_p]
         L.sfhk_serve_window.restype = C.c_int
+        L.sfhk_request_run.argtypes = [P, C.c_uint64, C.c_int32, C.c_void_p, C.c_size_t,
+                                       C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
+        L.sfhk_request_run.restype = C.c_int
         L.sfhk_request_finalize.argtypes = [P, C.c_int32, C.c_void_p, C.c_int32, C.c_int32,
                                             C.c_void_p]
         L.sfhk_request_finalize.restype = C.c_int

@@ -87,6 +87,8 @@ serve_slice_f64(const ReqDev* __restrict__ reqs, SliceTable tab) {
     }
 
   const double h = d.dt;
+  const ExpK ekv = make_expk();  // the exponential's constants in VGPRs
+  const ExpK* ek = &ekv;
   const double* __restrict__ fe = R.field;
   double* __restrict__ acc = R.accum;
   double acc_reg = 0.0;
@@ -116,7 +118,7 @@ serve_slice_f64(const ReqDev* __restrict__ reqs, SliceTable tab) {
     double K1[6], K2[6], K3[6], K4[6];
     double V, g[3];
     double sq[3], sp3[3], sS, yq[3], yp[3];
-    potential(d, Gk, V, g, K1);
+    potential(d, Gk, V, g, K1, ek);
     {
       const double kp[3] = {-g[0], -g[1], -g[2] - Ek};
       const double kS = 0.5 * (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]) - V - q[2] * Ek;
@@ -129,7 +131,7 @@ serve_slice_f64(const ReqDev* __restrict__ reqs, SliceTable tab) {
       }
       sS = kS;
     }
-    potential(d, hRn, yq, V, g, K2);
+    potential(d, hRn, yq, V, g, K2, ek);
     {
       const double kp[3] = {-g[0], -g[1], -g[2] - Eh};
       const double kS = 0.5 * (yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]) - V - yq[2] * Eh;
@@ -143,7 +145,7 @@ serve_slice_f64(const ReqDev* __restrict__ reqs, SliceTable tab) {
       }
       sS += 2.0 * kS;
     }
-    potential(d, hRn, yq, V, g, K3);
+    potential(d, hRn, yq, V, g, K3, ek);
     {
       const double kp[3] = {-g[0], -g[1], -g[2] - Eh};
       const double kS = 0.5 * (yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]) - V - yq[2] * Eh;
@@ -157,7 +159,7 @@ serve_slice_f64(const ReqDev* __restrict__ reqs, SliceTable tab) {
       }
       sS += 2.0 * kS;
     }
-    potential(d, hRn, yq, V, g, K4);
+    potential(d, hRn, yq, V, g, K4, ek);
     {
       const double kp[3] = {-g[0], -g[1], -g[2] - E1};
       const double kS = 0.5 * (yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]) - V - yq[2] * E1;

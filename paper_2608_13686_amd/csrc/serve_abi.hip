@@ -61,6 +61,48 @@ int64_t steps_of(const sfhk_problem* p) {
   return d.N;
 }
 
+// The request's device view: its problem constants and its buffers carved
+// from `buffer` by req_layout.
+ReqDev carve_request(const sfhk_problem* p, uint64_t n_traj, uint64_t seed, uint64_t first_index,
+                     double h_step, int32_t n_omega, void* buffer, const ReqLayout& L) {
+  char* b = static_cast<char*>(buffer);
+  ReqDev r;
+  std::memset(&r, 0, sizeof r);
+  r.desc = make_desc_ext(*p);
+  r.desc.field_off = 0;
+  r.desc.acc_off = 0;
+  r.desc.slot_off = 0;
+  r.desc.n_slots = n_traj;
+  r.desc.seed = seed;
+  r.desc.first_index = first_index;
+  r.field = reinterpret_cast<double*>(b + L.field);
+  r.accum = reinterpret_cast<double*>(b + L.accum);
+  r.v = reinterpret_cast<double*>(b + L.v);
+  r.V_re = reinterpret_cast<double*>(b + L.vre);
+  r.V_im = reinterpret_cast<double*>(b + L.vim);
+  r.yield = reinterpret_cast<double*>(b + L.yield);
+  r.k0 = reinterpret_cast<int32_t*>(b + L.k0);
+  r.prob = reinterpret_cast<int32_t*>(b + L.prob);
+  double** f64[11] = {&r.qx, &r.qy, &r.qz, &r.px, &r.py, &r.pz, &r.w,
+                      &r.nx, &r.ny, &r.nz, &r.dph};
+  for (int i = 0; i < 11; ++i) *f64[i] = reinterpret_cast<double*>(b + L.f64[i]);
+  r.order = reinterpret_cast<uint32_t*>(b + L.order);
+  uint32_t* runs = reinterpret_cast<uint32_t*>(b + L.runs);
+  r.live_start = runs;
+  r.live_count = runs + 1;
+  r.pack_start = runs + 2;
+  r.state = reinterpret_cast<double*>(b + L.state);
+  r.live_cap = n_traj;
+  r.h_step = h_step;
+  r.n_omega = n_omega;
+  return r;
+}
+
+EnsPtrs ens_of(const ReqDev& r) {
+  return EnsPtrs{r.k0, r.prob, r.qx, r.qy, r.qz, r.px, r.py, r.pz, r.w, r.nx, r.ny, r.nz,
+                 r.dph, r.order, r.live_start, r.live_count, r.pack_start};
+}
+
 }  // namespace
 
 extern "C" {
@@ -103,42 +145,13 @@ sfhk_status sfhk_request_init(const sfhk_problem* p, uint64_t n_traj, uint64_t s
   ReqLayout L = req_layout(N, n_traj, n_omega);
   if (buffer_bytes < L.bytes) return fail_ext(SFHK_E_NOMEM, "request buffer too small");
   char* b = static_cast<char*>(buffer);
-  ReqDev r;
-  std::memset(&r, 0, sizeof r);
-  r.desc = make_desc_ext(*p);
-  r.desc.field_off = 0;
-  r.desc.acc_off = 0;
-  r.desc.slot_off = 0;
-  r.desc.n_slots = n_traj;
-  r.desc.seed = seed;
-  r.desc.first_index = first_index;
-  r.field = reinterpret_cast<double*>(b + L.field);
-  r.accum = reinterpret_cast<double*>(b + L.accum);
-  r.v = reinterpret_cast<double*>(b + L.v);
-  r.V_re = reinterpret_cast<double*>(b + L.vre);
-  r.V_im = reinterpret_cast<double*>(b + L.vim);
-  r.yield = reinterpret_cast<double*>(b + L.yield);
-  r.k0 = reinterpret_cast<int32_t*>(b + L.k0);
-  r.prob = reinterpret_cast<int32_t*>(b + L.prob);
-  double** f64[11] = {&r.qx, &r.qy, &r.qz, &r.px, &r.py, &r.pz, &r.w,
-                      &r.nx, &r.ny, &r.nz, &r.dph};
-  for (int i = 0; i < 11; ++i) *f64[i] = reinterpret_cast<double*>(b + L.f64[i]);
-  r.order = reinterpret_cast<uint32_t*>(b + L.order);
-  uint32_t* runs = reinterpret_cast<uint32_t*>(b + L.runs);
-  r.live_start = runs;
-  r.live_count = runs + 1;
-  r.pack_start = runs + 2;
-  r.state = reinterpret_cast<double*>(b + L.state);
-  r.live_cap = n_traj;
-  r.h_step = h_step;
-  r.n_omega = n_omega;
+  ReqDev r = carve_request(p, n_traj, seed, first_index, h_step, n_omega, buffer, L);
   ReqDev* dst = static_cast<ReqDev*>(table) + slot;
   hipStream_t s = static_cast<hipStream_t>(stream);
   uint32_t* hist = reinterpret_cast<uint32_t*>(b + L.hist);
   uint32_t* cursor = reinterpret_cast<uint32_t*>(b + L.cursor);
   uint64_t* slot_off = reinterpret_cast<uint64_t*>(b + L.slot_off);
-  EnsPtrs ep{r.k0, r.prob, r.qx, r.qy, r.qz, r.px, r.py, r.pz, r.w, r.nx, r.ny, r.nz,
-             r.dph, r.order, r.live_start, r.live_count, r.pack_start};
+  EnsPtrs ep = ens_of(r);
   const Desc* ddev = &dst->desc;
   hipError_t e = launch_write_req(r, dst, s);
   if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t*>(slot_off), 0u, 4, s);
@@ -190,6 +203,28 @@ sfhk_status sfhk_serve_window(void* table, int32_t table_slots, int32_t n, const
     hipError_t e = launch_serve_slice(static_cast<const ReqDev*>(table), tab, s);
     if (e != hipSuccess) return hip_fail_ext(e, "serve window");
   }
+  return ok_ext();
+}
+
+sfhk_status sfhk_request_run(const sfhk_problem* p, uint64_t n_traj, int32_t n_omega,
+                             void* buffer, size_t buffer_bytes, void* table, int32_t table_slots,
+                             int32_t slot, void* stream) {
+  sfhk_status st = check_problem_ext(p, 0);
+  if (st != SFHK_OK) return st;
+  if (!buffer || !table || slot < 0 || slot >= table_slots || n_omega < 0)
+    return fail_ext(SFHK_E_INVALID, "buffer/table/slot/n_omega invalid");
+  if (n_traj == 0 || n_traj >= (uint64_t(1) << 31))
+    return fail_ext(SFHK_E_INVALID, "n_traj must be in 1..2^31-1");
+  const ReqLayout L = req_layout(steps_of(p), n_traj, n_omega);
+  if (buffer_bytes < L.bytes) return fail_ext(SFHK_E_NOMEM, "request buffer too small");
+  // host-side pointers into the request's buffer; seed and grid do not enter
+  // the propagation
+  const ReqDev r = carve_request(p, n_traj, 0, 0, 0.0, n_omega, buffer, L);
+  const Desc* ddev = &(static_cast<const ReqDev*>(table) + slot)->desc;
+  const uint32_t max_packs = (uint32_t)((n_traj + kWave - 1) / kWave + 1);
+  hipError_t e = launch_propagate_f64(ddev, 1, r.field, ens_of(r), nullptr, max_packs, r.accum,
+                                      Records{}, static_cast<hipStream_t>(stream), LaunchCfg{});
+  if (e != hipSuccess) return hip_fail_ext(e, "request run");
   return ok_ext();
 }
 

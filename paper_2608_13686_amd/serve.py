@@ -86,20 +86,23 @@ class Request:
         self.handle = None
         self.event = None
         self.result = None
+        self.host_result = None
         self.state = "waiting"
 
 
 class HipExecutor:
     """Device side of the server: a torch uint8 pool, the request table and
     the C ABI calls.  Requests are sampled and finalised on the main stream;
-    their packs are split into `n_groups` interleaved groups, each advanced by
-    its own stream (group 0 by the main stream itself), so that the tail of
-    one group's window overlaps the others' windows.  All streams have the
-    default priority.  The streams need hardware queues of their own (a
-    process has 4 by default) for the overlap to happen."""
+    their packs can be split into `n_groups` interleaved groups, each advanced
+    by its own stream (group 0 by the main stream itself), so that the tail
+    of one group's window overlaps the others' windows.  All streams have the
+    default priority.  One group is the default: a lone request split over
+    two streams ran 1.3-1.4x slower than in one (measured on requests of
+    1e5-2e5 trajectories); the streams need hardware queues of their own (a
+    process has 4 by default) for any overlap to happen."""
 
     def __init__(self, pool_bytes, max_requests, n_omega, h_step, device="cuda", stream=None,
-                 n_groups=2):
+                 n_groups=1):
         import torch
         self.torch = torch
         self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=device)
@@ -149,8 +152,19 @@ class HipExecutor:
             gs.wait_event(ev)
 
     def window(self, entries, group=0):
-        """entries: list of (request, k_from, k_to); advances pack group `group`."""
+        """entries: list of (request, k_from, k_to); advances pack group `group`.
+        A lone request's window over its whole pulse runs the plain FP64
+        kernel of sfhk_propagate (sfhk_request_run): no state is kept
+        between windows it does not have."""
         n = len(entries)
+        if n == 1 and self.n_groups == 1:
+            r, k_from, k_to = entries[0]
+            if k_from == 0 and k_to == r.n_steps + 1:
+                _abi.check(_abi.lib().sfhk_request_run(
+                    r.handle, r.n_traj, self.n_omega, C.c_void_p(self.pool.data_ptr() + r.offset),
+                    r.bytes, C.c_void_p(self.table.data_ptr()), self.max_requests, r.slot,
+                    self._h), "sfhk_request_run")
+                return self._event(self.stream)
         slots = (C.c_int32 * n)(*[r.slot for r, _, _ in entries])
         ntraj = (C.c_uint64 * n)(*[r.n_traj for r, _, _ in entries])
         kf = (C.c_int32 * n)(*[a for _, a, _ in entries])
@@ -163,11 +177,29 @@ class HipExecutor:
         return self._event(gs)
 
     def finalize(self, req):
+        """Enqueues the request's dipole and spectrum and the copies of its
+        results into pinned host memory, right behind its last window (ahead
+        of any window queued later); the returned event marks the results
+        ready on the host."""
+        torch = self.torch
         for gs in self.group_streams[1:]:
             self.stream.wait_event(self._event(gs))
         _abi.check(_abi.lib().sfhk_request_finalize(
             req.handle, self.n_omega, C.c_void_p(self.table.data_ptr()),
             self.max_requests, req.slot, self._h), "sfhk_request_finalize")
+        offs = (C.c_size_t * 4)()
+        _abi.check(_abi.lib().sfhk_request_layout(req.handle, req.n_traj, self.n_omega, offs),
+                   "sfhk_request_layout")
+        base = req.offset
+        sizes = {"v": req.n_steps + 1, "V_re": self.n_omega, "V_im": self.n_omega,
+                 "yield": self.n_omega}
+        host = {}
+        with torch.cuda.stream(self.stream):
+            for (name, n), off in zip(sizes.items(), offs):
+                dev = self.pool[base + off: base + off + 8 * n].view(torch.float64)
+                host[name] = torch.empty(n, dtype=torch.float64, pin_memory=True)
+                host[name].copy_(dev, non_blocking=True)
+        req.host_result = host
         return self._event(self.stream)
 
     def retire(self, req):
@@ -183,18 +215,9 @@ class HipExecutor:
         ev.synchronize()
 
     def result(self, req):
-        torch = self.torch
-        offs = (C.c_size_t * 4)()
-        _abi.check(_abi.lib().sfhk_request_layout(req.handle, req.n_traj, self.n_omega, offs),
-                   "sfhk_request_layout")
-        base = req.offset
-        N = req.n_steps
-
-        def f64(off, n):
-            return self.pool[base + off: base + off + 8 * n].view(torch.float64).cpu()
-
-        out = {"v": f64(offs[0], N + 1), "V_re": f64(offs[1], self.n_omega),
-               "V_im": f64(offs[2], self.n_omega), "yield": f64(offs[3], self.n_omega)}
+        """The results copied by finalize (valid once its event is done)."""
+        out = req.host_result
+        req.host_result = None
         return out
 
 
@@ -204,21 +227,41 @@ class Server:
     `in_flight` launches queued on the device.
 
     Policies: ``"ps"`` advances every admitted request each step (processor
-    sharing); ``"srpt"`` advances the requests with the least remaining work
-    (trajectories x steps left) first, adding requests until the launch holds
-    at least `fill_waves` wavefronts, so the device stays full while short
-    requests overtake long ones.
+    sharing); ``"srpt"`` advances first the requests with the least
+    estimated time left alone on the device (`time_left_us`) less
+    `age_weight` x their waiting time, so that short requests overtake long
+    ones and a long one that has waited long enough goes first; it adds
+    requests until the launch holds at least `fill_waves` wavefronts (default:
+    4 x the `device_waves` the device keeps resident), so the device stays
+    full.  ``"backfill"`` always runs the oldest request and fills with the
+    others by least remaining work; ``"deadline"`` runs earliest arrival +
+    `slack` x (estimated time alone) first.  Measured on a Poisson stream of
+    1,000 mixed H2/N2 requests at 0.5 and 0.8 of the saturation rate: a fill
+    of 2,048 wavefronts doubled srpt's p99 at 0.8; aging (age_weight 0.5)
+    took p99 at 0.8 from 510 to 474 ms; one window in flight (in_flight=1:
+    an arrival waits for at most the running window) took p50 at 0.5 from
+    49 to 47 ms; backfill and deadline trailed srpt.
 
-    A launch with fewer wavefronts than the device keeps resident
-    (`device_waves`, 2 per SIMD on 1,024 SIMDs) leaves the device partly idle
-    whatever its length, and each window costs a tail; such launches run
-    windows up to `max_stretch` times longer (in proportion to the idle room)."""
+    Window length.  With `window_ms` (the default), a window lasts about
+    `window_ms`: `window_ms / t_step` steps, where one step of a launch of n
+    trajectories takes t_step = max(step_us, n x traj_step_us) (a launch
+    below ~6,000 wavefronts is bound by one wavefront's step latency, a larger
+    one by throughput: measured ~3 us and ~1e-5 us per trajectory-step), at
+    least `window` steps, and no longer than the shortest picked request
+    needs, so that it is finalised as soon as its pulse ends; a request
+    running alone with nothing waiting runs to the end of its pulse in one
+    window, the plain FP64 kernel (every window boundary re-synchronises all
+    of its wavefronts and saves and restores 376 B per trajectory).  With window_ms=None every window is `window`
+    steps, stretched up to `max_stretch` times for launches with fewer
+    wavefronts than the device keeps resident (`device_waves`, 2 per SIMD on
+    1,024 SIMDs)."""
 
-    def __init__(self, executor, pool_bytes, max_requests=64, window=1024, in_flight=2,
-                 policy="ps", fill_waves=16384, device_waves=2048, max_stretch=8,
+    def __init__(self, executor, pool_bytes, max_requests=64, window=1024, in_flight=1,
+                 policy="srpt", fill_waves=None, device_waves=2048, max_stretch=8,
+                 window_ms=40.0, step_us=4.0, traj_step_us=1e-5, slack=4.0, age_weight=0.5,
                  clock=time.perf_counter):
-        if policy not in ("ps", "srpt"):
-            raise ValueError("policy must be 'ps' or 'srpt'")
+        if policy not in ("ps", "srpt", "backfill", "deadline"):
+            raise ValueError("policy must be 'ps', 'srpt', 'backfill' or 'deadline'")
         if window < 1 or in_flight < 1 or max_requests < 1:
             raise ValueError("window, in_flight and max_requests must be positive")
         self.x = executor
@@ -227,9 +270,16 @@ class Server:
         self.window = int(window)
         self.in_flight = in_flight
         self.policy = policy
-        self.fill_waves = int(fill_waves)
         self.device_waves = int(device_waves)
+        self.fill_waves = 4 * self.device_waves if fill_waves is None else int(fill_waves)
         self.max_stretch = max(1, int(max_stretch))
+        self.window_ms = None if window_ms is None else float(window_ms)
+        self.step_us = float(step_us)
+        self.traj_step_us = float(traj_step_us)
+        self.slack = float(slack)
+        self.age_weight = float(age_weight)
+        if self.window_ms is not None and (self.window_ms <= 0 or self.step_us <= 0):
+            raise ValueError("window_ms and step_us must be positive")
         self.clock = clock
         self.failed = []
         self.timed_out = []
@@ -322,27 +372,68 @@ class Server:
             if r.deadline is not None and now > r.deadline and r.state == "active":
                 r.state = "timing_out"
         run = [r for r in self.active if r.state == "active"]
+        if self.policy == "ps":
+            return run
         if self.policy == "srpt":
-            run.sort(key=self.remaining)
-            chosen, waves = [], 0
-            for r in run:
-                if waves >= self.fill_waves:
-                    break
-                chosen.append(r)
-                waves += (r.n_traj + 63) // 64
-            run = chosen
-        return run
+            # least estimated time left first, less the waiting time times
+            # age_weight (a request that has waited long enough goes first)
+            run.sort(key=lambda r: self.time_left_us(r) - self.age_weight * 1e6 * (now - r.arrival))
+        elif self.policy == "backfill":
+            # the oldest request always runs; the rest fill by least work left
+            head = min(run, key=lambda r: r.arrival) if run else None
+            run = ([head] if head else []) + sorted((r for r in run if r is not head),
+                                                   key=self.remaining)
+        else:  # "deadline": arrival + slack x (estimated time alone), earliest first
+            run.sort(key=self.deadline)
+        chosen, waves = [], 0
+        for r in run:
+            if waves >= self.fill_waves:
+                break
+            chosen.append(r)
+            waves += (r.n_traj + 63) // 64
+        return chosen
+
+    def time_left_us(self, r):
+        """Estimated time of the request's remaining steps alone on the device."""
+        steps = r.n_steps + 1 - r.k_next
+        return max(steps * self.step_us, r.n_traj * steps * self.traj_step_us)
+
+    def deadline(self, r):
+        steps = r.n_steps + 1
+        alone = max(steps * self.step_us, r.n_traj * steps * self.traj_step_us)
+        return r.arrival + self.slack * alone * 1e-6
 
     def window_for(self, picked):
         """Window length of the next launch (steps)."""
         waves = sum((r.n_traj + 63) // 64 for r in picked)
-        stretch = min(self.max_stretch, max(1, self.device_waves // max(waves, 1)))
-        return self.window * stretch
+        if self.window_ms is None:
+            stretch = min(self.max_stretch, max(1, self.device_waves // max(waves, 1)))
+            return self.window * stretch
+        rest = [r.n_steps + 1 - r.k_next for r in picked]
+        if len(picked) == 1 and len(self.active) == 1 and not self.waiting:
+            return max(1, rest[0])
+        traj = sum(r.n_traj for r in picked) / max(self.n_groups, 1)
+        step = max(self.step_us, traj * self.traj_step_us)  # one step of the launch
+        steps = int(self.window_ms * 1e3 / step)
+        return max(1, min(max(self.window, steps), min(rest)))
 
-    def step(self):
+    def device_busy(self):
+        """True while some pack group has `in_flight` windows outstanding."""
+        for evs in self._events:
+            while evs and self.x.done(evs[0]):
+                evs.popleft()
+            if len(evs) >= self.in_flight:
+                return True
+        return False
+
+    def step(self, block=True):
         """One window over the picked requests, launched for every pack group;
         requests that reach the end of their pulse are finalised.  Returns the
-        number of requests run."""
+        number of requests run.  With block=False nothing is launched (and 0
+        returned) while the device already holds `in_flight` windows, so that
+        the caller can take arrivals and finished requests meanwhile."""
+        if not block and self.device_busy():
+            return 0
         picked = self.pick()
         win = self.window_for(picked)
         entries = [(r, r.k_next, min(r.k_next + win, r.n_steps + 1)) for r in picked]
@@ -411,9 +502,11 @@ class Server:
             self.poll()
 
 
-def serve_stream(server, stream, t_limit=None, sleep=time.sleep):
+def serve_stream(server, stream, t_limit=None, sleep=time.sleep, poll_s=2e-4):
     """Replay a request stream [(arrival_s, problem, n_traj, seed)] in real
-    time through the server.  Returns the completed requests."""
+    time through the server.  The host never blocks on the device: while the
+    device holds its windows it takes arrivals and collects finished
+    requests, polling every `poll_s`.  Returns the completed requests."""
     t0 = server.clock()
     pending = deque(sorted(enumerate(stream), key=lambda x: x[1][0]))
     while pending or server.busy:
@@ -424,13 +517,15 @@ def serve_stream(server, stream, t_limit=None, sleep=time.sleep):
             i, (arr, prob, n, seed) = pending.popleft()
             server.submit(i, prob, n, seed, arrival=t0 + arr)
         server.admit()
-        if server.active:
-            server.step()
-        elif not server.finishing and pending:
-            sleep(max(0.0, min(0.01, pending[0][1][0] - (server.clock() - t0))))
-        elif server.finishing:
-            sleep(0.0002)
-        server.poll()
+        launched = server.step(block=False) if server.active else 0
+        finished = server.poll()
+        if launched or finished:
+            continue
+        # nothing to do before the next arrival, window end or result
+        gap = pending[0][1][0] - (server.clock() - t0) if pending else poll_s
+        if server.active or server.finishing or server.retiring:
+            gap = min(gap, poll_s)
+        sleep(max(0.0, min(gap, 0.01)))
     return server.completed
 
 

@@ -32,10 +32,12 @@ def rel(a, b):
     return r
 
 
-def server(pool_bytes=1 << 30, max_requests=8, window=1024, policy="ps", n_groups=2):
+def server(pool_bytes=1 << 30, max_requests=8, window=1024, policy="ps", n_groups=2,
+           window_ms=None):
     from paper_2608_13686_amd.serve import HipExecutor, Server
     x = HipExecutor(pool_bytes, max_requests, N_OMEGA, H_STEP, n_groups=n_groups)
-    return Server(x, pool_bytes, max_requests=max_requests, window=window, policy=policy)
+    return Server(x, pool_bytes, max_requests=max_requests, window=window, policy=policy,
+                  window_ms=window_ms)
 
 
 def requests():
@@ -59,11 +61,15 @@ def stepwise(sf, prob, n, seed):
     return out["v"][0].cpu().numpy(), out["V"][0].cpu().numpy(), out["yield"][0].cpu().numpy()
 
 
-@pytest.mark.parametrize("window,n_groups", [(64, 1), (777, 3), (1 << 20, 2)])
-def test_served_request_matches_oracle(sf, orc, window, n_groups):
+@pytest.mark.parametrize("window,n_groups,window_ms",
+                         [(64, 1, None), (777, 3, None), (1 << 20, 2, None), (64, 1, 40.0)])
+def test_served_request_matches_oracle(sf, orc, window, n_groups, window_ms):
+    """window_ms=40: the request runs alone, so its one window covers the
+    whole pulse and takes the plain FP64 kernel (sfhk_request_run)."""
     prob, n, seed = requests()[0]
-    S = server(window=window, n_groups=n_groups)
-    print(f"H2 {n} trajectories, window {window}, {n_groups} pack groups", flush=True)
+    S = server(window=window, n_groups=n_groups, window_ms=window_ms)
+    print(f"H2 {n} trajectories, window {window}, {n_groups} pack groups, "
+          f"window_ms {window_ms}", flush=True)
     S.submit("a", prob, n, seed)
     S.drain()
     (r,) = S.completed
@@ -97,20 +103,23 @@ def test_served_mix_matches_stepwise_path(sf):
         assert rel(r.result["yield"].numpy(), Y) < 1e-11
 
 
-@pytest.mark.parametrize("policy", ["ps", "srpt"])
+@pytest.mark.parametrize("policy,window_ms", [("ps", None), ("srpt", None), ("srpt", 0.3)])
 @pytest.mark.parametrize("which", [1, 3])
-def test_request_alone_equals_in_mix(sf, policy, which):
+def test_request_alone_equals_in_mix(sf, policy, window_ms, which):
     """The same request served alone and joined mid-flight by others (which
     then run windows offset from its own) gives the same dipole; every
     trajectory takes the same arithmetic alone and in the mix, so even the
-    chaotic request agrees up to the order of the dipole sums."""
+    chaotic request agrees up to the order of the dipole sums.  window_ms:
+    windows of about that duration, ending with the shortest request of each
+    launch (alone: one window for the whole pulse), one pack group."""
     reqs = requests()
     others = [i for i in range(len(reqs)) if i != which]
-    S = server(window=300, policy=policy)
+    groups = 1 if window_ms else 2
+    S = server(window=300, policy=policy, window_ms=window_ms, n_groups=groups)
     S.submit("alone", *reqs[which])
     S.drain()
     alone = S.completed[0].result
-    S = server(window=300, policy=policy, max_requests=4)
+    S = server(window=300, policy=policy, max_requests=4, window_ms=window_ms, n_groups=groups)
     S.submit("x0", *reqs[others[0]])
     S.admit()
     S.step()

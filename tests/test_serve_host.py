@@ -120,7 +120,8 @@ def _prob(N):
 
 def test_server_windows_cover_each_request_once():
     x = FakeExec()
-    S = Server(x, pool_bytes=1 << 22, max_requests=4, window=100, in_flight=2, max_stretch=1)
+    S = Server(x, pool_bytes=1 << 22, max_requests=4, window=100, in_flight=2, max_stretch=1,
+               window_ms=None, policy="ps")
     sizes = [(250, 1000), (99, 64), (1000, 3000), (100, 5), (0, 10), (333, 7000)]
     for i, (N, n) in enumerate(sizes):
         S.submit(i, _prob(N), n, seed=i)
@@ -141,7 +142,7 @@ def test_server_windows_cover_each_request_once():
 def test_admission_never_exceeds_pool_and_slots():
     x = FakeExec()
     pool = 600_000
-    S = Server(x, pool_bytes=pool, max_requests=3, window=64)
+    S = Server(x, pool_bytes=pool, max_requests=3, window=64, window_ms=None)
     rng = random.Random(3)
     tags = 0
     for _ in range(40):
@@ -162,7 +163,7 @@ def test_admission_never_exceeds_pool_and_slots():
 def test_big_request_waits_small_ones_pass_and_oversized_is_rejected():
     x = FakeExec()
     fp = x.footprint(None, 1000)
-    S = Server(x, pool_bytes=2 * fp, max_requests=8, window=50)
+    S = Server(x, pool_bytes=2 * fp, max_requests=8, window=50, window_ms=None)
     S.submit("a", _prob(500), 1000, 0)
     S.admit()
     S.submit("big", _prob(100), 1500, 1)  # needs more than what is left
@@ -177,7 +178,7 @@ def test_big_request_waits_small_ones_pass_and_oversized_is_rejected():
 
 def test_cancel_waiting_and_active():
     x = FakeExec()
-    S = Server(x, pool_bytes=1 << 22, max_requests=1, window=10)
+    S = Server(x, pool_bytes=1 << 22, max_requests=1, window=10, window_ms=None)
     S.submit("run", _prob(100), 100, 0)
     S.submit("wait", _prob(100), 100, 1)
     S.admit()
@@ -194,7 +195,8 @@ def test_cancel_waiting_and_active():
 def test_timeout_waiting_and_active():
     t = [0.0]
     x = FakeExec()
-    S = Server(x, pool_bytes=1 << 22, max_requests=1, window=10, clock=lambda: t[0])
+    S = Server(x, pool_bytes=1 << 22, max_requests=1, window=10, clock=lambda: t[0],
+               window_ms=None)
     S.submit("a", _prob(1000), 100, 0, timeout=5.0)
     S.submit("b", _prob(10), 100, 1, timeout=1.0)
     S.admit()
@@ -210,7 +212,7 @@ def test_timeout_waiting_and_active():
 
 def test_refused_admission_releases_memory():
     x = FakeExec(fail_tags={"bad"})
-    S = Server(x, pool_bytes=1 << 22, max_requests=2, window=100)
+    S = Server(x, pool_bytes=1 << 22, max_requests=2, window=100, window_ms=None)
     S.submit("bad", _prob(100), 10, 0)
     S.submit("good", _prob(100), 10, 1)
     S.drain()
@@ -222,7 +224,7 @@ def test_refused_admission_releases_memory():
 def test_srpt_picks_least_remaining_work_and_fills():
     x = FakeExec()
     S = Server(x, pool_bytes=1 << 30, max_requests=8, window=100, policy="srpt",
-               fill_waves=20)
+               fill_waves=20, window_ms=None)
     S.submit("long", _prob(10_000), 640, 0)   # 10 waves, much work
     S.submit("short", _prob(100), 640, 1)     # 10 waves, little work
     S.submit("mid", _prob(1000), 640, 2)
@@ -232,6 +234,78 @@ def test_srpt_picks_least_remaining_work_and_fills():
     assert x.launches[1][0] == 1 and x.launches[1][1] == x.launches[0][1]
     S.drain()
     assert [r.tag for r in S.completed][:2] == ["short", "mid"]
+
+
+def test_srpt_default_fill_is_four_devices():
+    x = FakeExec()
+    S = Server(x, pool_bytes=1 << 30, max_requests=8, window=100, device_waves=16,
+               window_ms=None)
+    assert S.policy == "srpt" and S.fill_waves == 64
+    S.submit("a", _prob(100), 1920, 0)   # 30 waves
+    S.submit("b", _prob(200), 2560, 1)   # 40 waves: reaches the fill
+    S.submit("c", _prob(300), 6400, 2)  # most work: waits
+    S.admit()
+    S.step()
+    assert [t for t, _, _ in x.launches[0][1]] == ["a", "b"]
+
+
+def test_backfill_runs_the_oldest_and_deadline_orders_by_slack():
+    x = FakeExec()
+    S = Server(x, pool_bytes=1 << 30, max_requests=8, window=100, policy="backfill",
+               fill_waves=20, window_ms=None)
+    S.submit("old_long", _prob(10_000), 640, 0, arrival=0.0)
+    S.submit("short", _prob(100), 640, 1, arrival=1.0)
+    S.submit("mid", _prob(1000), 640, 2, arrival=2.0)
+    S.admit()
+    S.step()
+    assert [t for t, _, _ in x.launches[0][1]] == ["old_long", "short"]
+    # deadline = arrival + slack x max(steps x step_us, n x steps x traj_step_us)
+    x = FakeExec()
+    S = Server(x, pool_bytes=1 << 30, max_requests=8, window=100, policy="deadline",
+               fill_waves=1, window_ms=None, step_us=1.0, traj_step_us=0.0, slack=2.0)
+    S.submit("a", _prob(999_999), 64, 0, arrival=0.0)   # deadline 0 + 2 x 1.0 s
+    S.submit("b", _prob(99_999), 64, 1, arrival=1.9)    # deadline 1.9 + 2 x 0.1 s > 2.0
+    S.admit()
+    S.step()
+    assert [t for t, _, _ in x.launches[0][1]] == ["a"]
+    x = FakeExec()
+    S = Server(x, pool_bytes=1 << 30, max_requests=8, window=100, policy="deadline",
+               fill_waves=1, window_ms=None, step_us=1.0, traj_step_us=0.0, slack=2.0)
+    S.submit("a", _prob(999_999), 64, 0, arrival=0.0)
+    S.submit("b", _prob(99_999), 64, 1, arrival=1.0)    # deadline 1.2 < 2.0
+    S.admit()
+    S.step()
+    assert [t for t, _, _ in x.launches[0][1]] == ["b"]
+
+
+def test_non_blocking_step_waits_for_a_free_window():
+    class SlowExec(FakeExec):
+        n_groups = 1
+
+        def __init__(self):
+            super().__init__()
+            self.finished = set()
+
+        def done(self, ev):
+            return ev in self.finished
+
+    x = SlowExec()
+    S = Server(x, pool_bytes=1 << 22, max_requests=4, window=10, in_flight=2, window_ms=None,
+               max_stretch=1)
+    S.submit("r", _prob(100), 64, 0)  # 11 windows of 10 steps
+    S.admit()
+    assert S.step(block=False) == 1 and S.step(block=False) == 1
+    assert S.device_busy()
+    assert S.step(block=False) == 0 and len(x.launches) == 2 and x.waits == 0
+    x.finished.add(1)  # the first window ends
+    assert not S.device_busy()
+    assert S.step(block=False) == 1 and len(x.launches) == 3
+    assert S.step(block=False) == 0
+    x.finished.update(range(0, 100))  # every later window (and the finalize, 0) ends at once
+    while S.busy:
+        S.step(block=False)
+        S.poll()
+    assert [r.tag for r in S.completed] == ["r"] and x.waits == 0
 
 
 def test_serve_stream_and_fifo_with_fake_clock():
@@ -246,7 +320,7 @@ def test_serve_stream_and_fifo_with_fake_clock():
 
     stream = [(0.01 * i, _prob(50 + 10 * i), 100 + i, i) for i in range(12)]
     x = FakeExec()
-    S = Server(x, pool_bytes=1 << 22, max_requests=4, window=32, clock=clock)
+    S = Server(x, pool_bytes=1 << 22, max_requests=4, window=32, clock=clock, window_ms=None)
     done = serve_stream(S, stream, sleep=sleep)
     assert sorted(r.tag for r in done) == list(range(12))
     st = latency_stats(done)
@@ -261,7 +335,7 @@ def test_serve_stream_and_fifo_with_fake_clock():
 def test_small_launches_stretch_their_window():
     x = FakeExec()
     S = Server(x, pool_bytes=1 << 26, max_requests=4, window=100, device_waves=64,
-               max_stretch=8)
+               max_stretch=8, window_ms=None, policy="ps")
     S.submit("small", _prob(5000), 64 * 10, 0)   # 10 waves: window x 6
     S.admit()
     S.step()
@@ -275,11 +349,52 @@ def test_small_launches_stretch_their_window():
     assert w[-1][1] == 5001 and all(w[i][1] == w[i + 1][0] for i in range(len(w) - 1))
 
 
+def test_time_targeted_windows():
+    """A lone request runs to the end of its pulse in one window; with others
+    active a window lasts about window_ms (one step of a launch of n
+    trajectories: max(step_us, n traj_step_us)), at least `window` steps, and
+    ends with the shortest picked request."""
+    x = FakeExec()
+    x.n_groups = 1
+    S = Server(x, pool_bytes=1 << 30, max_requests=8, window=50, device_waves=64,
+               window_ms=1.0, step_us=2.0, traj_step_us=1e-3)
+    S.submit("alone", _prob(5000), 64 * 10, 0)
+    S.admit()
+    S.step()
+    assert x.launches[0][1] == [("alone", 0, 5001)]
+    S.drain()
+    x = FakeExec()
+    x.n_groups = 1
+    S = Server(x, pool_bytes=1 << 30, max_requests=8, window=50, device_waves=64,
+               window_ms=1.0, step_us=2.0, traj_step_us=1e-3)
+    S.submit("a", _prob(5000), 64 * 40, 0)    # 2560 trajectories
+    S.submit("b", _prob(9000), 64 * 40, 1)    # 5120 in all: 5.12 us per step -> 195 steps
+    S.admit()
+    S.step()
+    assert x.launches[0][1] == [("a", 0, 195), ("b", 0, 195)]
+    S.submit("c", _prob(100), 64, 2)          # shortest: the window ends with it
+    S.admit()
+    S.step()
+    assert x.launches[1][1] == [("c", 0, 101), ("a", 195, 296), ("b", 195, 296)]
+    S.drain()
+    for r in S.completed:
+        w = r.result["windows"]
+        assert w[0][0] == 0 and w[-1][1] == r.n_steps + 1
+        assert all(w[i][1] == w[i + 1][0] for i in range(len(w) - 1))
+    # every launch is at least `window` steps unless one of its requests ends
+    ends = {r.tag: r.n_steps + 1 for r in S.completed}
+    for _, ent in x.launches:
+        assert all(b - a == ent[0][2] - ent[0][1] for _, a, b in ent)
+        assert ent[0][2] - ent[0][1] >= 50 or any(b == ends[t] for t, _, b in ent)
+
+
 def test_server_rejects_bad_config():
     with pytest.raises(ValueError):
-        Server(FakeExec(), 1 << 20, policy="lifo")
+        Server(FakeExec(), 1 << 20, policy="lifo", window_ms=None)
     with pytest.raises(ValueError):
-        Server(FakeExec(), 1 << 20, window=0)
+        Server(FakeExec(), 1 << 20, window=0, window_ms=None)
+    with pytest.raises(ValueError):
+        Server(FakeExec(), 1 << 20, window_ms=-1.0)
 
 
 # -------------------------------------------------- C ABI (host-side checks)
