@@ -494,7 +494,7 @@ def averaging_study(sf, mol, ionization, sizes, reps, n_ref, cap=False):
             "seconds": time.perf_counter() - t}
 
 
-def averaging_variant(sf, sizes=(1 << 14, 1 << 16, 1 << 18, 1 << 20), reps=3):
+def averaging_variant(sf, sizes=(1 << 14, 1 << 16, 1 << 18, 1 << 20), reps=4):
     """The averaging study for H2 and N2, each with the first-order sampler
     and with the saddle-point sampler whose weight carries the axis-dependent
     ionisation element (the Eq. 6 weight), each as sampled and with the
@@ -505,7 +505,7 @@ def averaging_variant(sf, sizes=(1 << 14, 1 << 16, 1 << 18, 1 << 20), reps=3):
         for ion in ("first_order", "saddle"):
             for cap in (False, True):
                 key = f"{mol}-{ion}" + ("-capped" if cap else "")
-                out[key] = averaging_study(sf, mol, ion, sizes, reps if not cap else 2, n_ref,
+                out[key] = averaging_study(sf, mol, ion, sizes, reps, n_ref,
                                            cap)
                 print(f"averaging {key}: {out[key]}", file=sys.stderr, flush=True)
     return out
