@@ -1,5 +1,7 @@
-// FP64 trajectory kernel for launches far below device fill (latency form):
-// one trajectory per group of 8 lanes, 8 trajectories per wavefront.
+// FP64 trajectory kernels for launches far below device fill (latency form):
+// one trajectory per group of 8 lanes, 8 trajectories per wavefront; without
+// records the orbit runs on a second wavefront a step ahead (pipelined form
+// below).
 //
 // Lane c of a group holds column c of the 6x6 monodromy matrix (c < 6; lanes
 // 6 and 7 hold a zero column, which the linear update keeps at zero) and
@@ -292,6 +294,380 @@ __device__ __forceinline__ bool find_unit(const EnsPtrs& e, int n_prob, uint32_t
   return unit_pos < e.live_count[lo];
 }
 
+// ------------------------------------------------------------ pipelined
+// The same latency form on two wavefronts per unit of 8 trajectories, so that
+// the two halves of a step run on two SIMDs at once: wavefront 0 (the orbit
+// wavefront, lane g for trajectory g) integrates (q, p, S) and evaluates the
+// four stage Hessians; wavefront 1 (the monodromy wavefront, 8 lanes per
+// trajectory as above) takes the prefactor, amplitude and deposit at step k
+// and advances its columns with the Hessians of step k.  The orbit wavefront
+// runs one step ahead: in iteration i it writes step i's state and Hessians
+// into ring slot i mod 2 of LDS while the monodromy wavefront reads step
+// i - 1's from the other slot; one workgroup barrier per iteration hands the
+// slots over.  The monodromy wavefront also spreads the recombination
+// amplitude's shells over the 8 lanes of the group and keeps each step's
+// amplitudes in LDS, summing them across trajectories once every 64 steps.
+// The orbit, the columns and the prefactor take the one-wavefront form's
+// operations on the same operands in the same order; the amplitude's and
+// the dipole's sums are ordered differently (rounding-level differences).
+// The orbit of a trajectory stopped by the prefactor cap is integrated on
+// but not used; records (which hold the stopping step's state) use the
+// one-wavefront form.
+constexpr int kPipeThreads = 2 * kWave;
+
+// 32-bit DPP move of both halves of a double (control code Ctl)
+template <int Ctl>
+__device__ __forceinline__ double dpp64(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, Ctl, 0xf, 0xf,
+                                                            true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), Ctl, 0xf,
+                                                            0xf, true);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over the 8 lanes of a group, on every lane of it: lanes i ^ 1 and
+// i ^ 2 through quad permutations, then the two quads through the half-row
+// mirror (lane i <-> 7 - i).  Every lane adds the same operands in the same
+// order up to commutation, so all hold the same value.
+__device__ __forceinline__ double group_sum(double x) {
+  x += dpp64<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+  x += dpp64<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+  return x + dpp64<0x141>(x);  // row_half_mirror
+}
+
+// The recombination amplitude of amplitude_re with the shells spread over
+// the 8 lanes of the trajectory's group (lane c takes shells c, c + 8, ...),
+// the phase factor evaluated on every lane beside them, and the shells'
+// sums gathered by group_sum: the same terms as amplitude_re, summed in a
+// different order.  Every lane of the group returns the value.
+__device__ __forceinline__ double amplitude_re_group(const Desc& d, const double n[3],
+                                                     const double p[3], const Geom<double>& G,
+                                                     double Cre, double Cim, double S,
+                                                     double tk, double t0, double p0q0,
+                                                     double w, int c) {
+  const double pp = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+  const double dd[2] = {G.r2[0] - d.eps2[0], G.r2[1] - d.eps2[1]};
+  const double cc = 1.0 + Cre * Cre + Cim * Cim;
+  const double lnC = 0.3466 * (double)(((int)(__double_as_longlong(cc) >> 52) & 0x7ff) - 1022);
+  if (fmin(dd[0], dd[1]) * d.g_inv4k_min + kRecombFar > lnC) return 0.0;  // group-uniform
+  const double np_ = n[0] * p[0] + n[1] * p[1] + n[2] * p[2];
+  const double bzr = p[2] * d.inv_gamma;
+  const double nbr = np_ * d.inv_gamma;
+  const double bb_re_p = pp * d.inv_gamma2;
+  const double ppg = pp * d.half_inv_gamma;
+  double rr = 0.0, ri = 0.0;
+  for (int j = c; j < d.n_shell; j += kGroup) {
+    const int ce = j < d.n_shell0 ? 0 : 1;
+    const double dz = -G.dz[ce];
+    const double pd = -(p[0] * G.dx[ce] + p[1] * G.dy[ce] + p[2] * G.dz[ce]);
+    const double nd = -(n[0] * G.dx[ce] + n[1] * G.dy[ce] + n[2] * G.dz[ce]);
+    const double i4 = d.sh_inv4k[j], i2 = 2.0 * i4;
+    const double er = (bb_re_p - dd[ce]) * i4 - ppg;
+    if (er + lnC < kRecombFar) continue;
+    const double ei = 2.0 * pd * d.inv_gamma * i4;
+    const double gm = exp_neg(-er);
+    double sn, cs;
+    sincos_k(ei, sn, cs);
+    const double Gr = gm * cs, Gi = gm * sn;
+    double Xr = d.sh_ns[j] * bzr * i2, Xi = d.sh_ns[j] * dz * i2;
+    if (d.sh_np[j] != 0.0) {
+      const double ur = n[2] * i2 + (bzr * nbr - dz * nd) * i2 * i2;
+      const double ui = (bzr * nd + dz * nbr) * i2 * i2;
+      Xr -= d.sh_np[j] * ui;
+      Xi += d.sh_np[j] * ur;
+    }
+    rr += Gr * Xr - Gi * Xi;
+    ri += Gr * Xi + Gi * Xr;
+  }
+  const double phi = S - d.Ip * (tk - t0) + p0q0;
+  double sp, cp;
+  sincos_k(phi, sp, cp);
+  rr = group_sum(rr);
+  ri = group_sum(ri);
+  if (rr == 0.0 && ri == 0.0) return 0.0;
+  const double er_ = Cre * cp - Cim * sp, ei_ = Cre * sp + Cim * cp;
+  return -w * (er_ * rr - ei_ * ri);
+}
+
+struct PipeRing {
+  double K[2][4][6][kPerWave];  // slot, RK4 stage, Hessian entry, trajectory
+  double st[2][7][kPerWave];    // slot, (q, p, S) at the step, trajectory
+  double dep[kWave][kPerWave];  // Re a of the last 64 steps (step mod 64, trajectory)
+};
+
+__device__ __forceinline__ void run_pipe_unit(const Desc* __restrict__ descs,
+                                              const double* __restrict__ field, const EnsPtrs& e,
+                                              const int32_t* __restrict__ dep_from,
+                                              double* __restrict__ accum, int prob,
+                                              uint32_t unit_pos, PipeRing& ring) {
+  const Desc& d = descs[prob];
+  const int N = d.N;
+  const bool orbit_wave = threadIdx.x < kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int g = orbit_wave ? lane : lane / kGroup;  // trajectory of the unit
+  const int c = lane & (kGroup - 1);                 // monodromy column
+  const uint32_t pos = unit_pos + (uint32_t)g;
+  const bool valid = g < kPerWave && pos < e.live_count[prob];
+  const uint32_t slot = valid ? e.order[e.live_start[prob] + pos] : 0u;
+  const int k0 = valid ? e.k0[slot] : N + 1;
+  // the unit's first trajectory is born first (sorted by birth step)
+  const int kmin = e.k0[e.order[e.live_start[prob] + unit_pos]];
+  const double h = d.rk.h, hh = d.rk.hh, h6 = d.rk.h6;
+  double q[3] = {e.qx[slot], e.qy[slot], e.qz[slot]};
+  double p[3] = {e.px[slot], e.py[slot], e.pz[slot]};
+  const double n[3] = {e.nx[slot], e.ny[slot], e.nz[slot]};
+  const double hRn[3] = {d.half_R * n[0], d.half_R * n[1], d.half_R * n[2]};
+  double S = 0.0;
+
+  if (orbit_wave) {
+    const double* __restrict__ fe = field + d.field_off;
+    const ExpK ekv = make_expk();
+    for (int i = kmin; i <= N + 1; ++i) {
+      if (valid && i <= N) {
+        const int sl = i & 1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          ring.st[sl][a][g] = q[a];
+          ring.st[sl][3 + a][g] = p[a];
+        }
+        ring.st[sl][6][g] = S;
+        if (i >= k0 && i < N) {
+          const double Ek = fe[2 * i], Eh = fe[2 * i + 1], E1 = fe[2 * i + 2];
+          double K[6], V, gr[3];
+          double sq[3], sp3[3], sS, yq[3], yp[3];
+          Geom<double> Gk;
+          geometry(d, hRn, q, Gk);
+          potential(d, Gk, V, gr, K, &ekv);
+#pragma unroll
+          for (int j = 0; j < 6; ++j) ring.K[sl][0][j][g] = K[j];
+          {
+            const double kp[3] = {-gr[0], -gr[1], -gr[2] - Ek};
+            sS = 0.5 * (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]) - V - q[2] * Ek;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              sq[a] = p[a];
+              sp3[a] = kp[a];
+              yq[a] = q[a] + hh * p[a];
+              yp[a] = p[a] + hh * kp[a];
+            }
+          }
+          potential(d, hRn, yq, V, gr, K, &ekv);
+#pragma unroll
+          for (int j = 0; j < 6; ++j) ring.K[sl][1][j][g] = K[j];
+          {
+            const double kp[3] = {-gr[0], -gr[1], -gr[2] - Eh};
+            sS += 2.0 * (0.5 * (yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]) - V - yq[2] * Eh);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              const double kq = yp[a];
+              sq[a] += 2.0 * kq;
+              sp3[a] += 2.0 * kp[a];
+              yq[a] = q[a] + hh * kq;
+              yp[a] = p[a] + hh * kp[a];
+            }
+          }
+          potential(d, hRn, yq, V, gr, K, &ekv);
+#pragma unroll
+          for (int j = 0; j < 6; ++j) ring.K[sl][2][j][g] = K[j];
+          {
+            const double kp[3] = {-gr[0], -gr[1], -gr[2] - Eh};
+            sS += 2.0 * (0.5 * (yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]) - V - yq[2] * Eh);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              const double kq = yp[a];
+              sq[a] += 2.0 * kq;
+              sp3[a] += 2.0 * kp[a];
+              yq[a] = q[a] + h * kq;
+              yp[a] = p[a] + h * kp[a];
+            }
+          }
+          potential(d, hRn, yq, V, gr, K, &ekv);
+#pragma unroll
+          for (int j = 0; j < 6; ++j) ring.K[sl][3][j][g] = K[j];
+          {
+            const double kp[3] = {-gr[0], -gr[1], -gr[2] - E1};
+            sS += 0.5 * (yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]) - V - yq[2] * E1;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              sq[a] += yp[a];
+              sp3[a] += kp[a];
+              q[a] = q[a] + h6 * sq[a];
+              p[a] = p[a] + h6 * sp3[a];
+            }
+            S = S + h6 * sS;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    return;
+  }
+
+  // monodromy wavefront
+  const int kdep = (dep_from != nullptr && valid) ? dep_from[slot] : 0;
+  const double w = e.w[slot];
+  const double t0 = d.t_first + (double)k0 * d.dt;
+  const double p0q0 = p[0] * q[0] + p[1] * q[1] + p[2] * q[2] + e.dph[slot];
+  double x[3], v[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    x[r] = (c == r) ? 1.0 : 0.0;
+    v[r] = (c == r + 3) ? 1.0 : 0.0;
+  }
+  double Cre = 1.0, Cim = 0.0, flips = 0.0;
+  double* __restrict__ acc = accum + d.acc_off;
+  const double gamma = d.gamma, inv_gamma = d.inv_gamma;
+  int kend = N + 1;
+  __syncthreads();  // iteration kmin: the orbit wavefront writes step kmin
+  for (int k = kmin; k <= N; ++k) {
+    const int sl = k & 1;
+    bool live = k >= k0 && k < kend;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      q[a] = ring.st[sl][a][g];
+      p[a] = ring.st[sl][3 + a][g];
+    }
+    S = ring.st[sl][6][g];
+    double x3[3], v3[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      x3[r] = from_lane_plus<3>(x[r]);
+      v3[r] = from_lane_plus<3>(v[r]);
+    }
+    double rr[3], ri[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      rr[r] = x[r] + v3[r];
+      ri[r] = fma(inv_gamma, v[r], -gamma * x3[r]);
+    }
+    double Rr[3][3], Ri[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      Rr[r][0] = rr[r];
+      Ri[r][0] = ri[r];
+      Rr[r][1] = from_lane_plus<1>(rr[r]);
+      Ri[r][1] = from_lane_plus<1>(ri[r]);
+      Rr[r][2] = from_lane_plus<2>(rr[r]);
+      Ri[r][2] = from_lane_plus<2>(ri[r]);
+    }
+    double re_a = 0.0;
+    if (live && c == 0) {
+      prefactor_step(Rr, Ri, Cre, Cim, flips);
+      if (d.c_max2 > 0.0 && Cre * Cre + Cim * Cim > d.c_max2) kend = k;
+    }
+    if (d.c_max2 > 0.0) {  // the cap decision of lane 0 holds for its whole group
+      kend = __shfl(kend, lane & ~(kGroup - 1), kWave);
+      live = k >= k0 && k < kend;
+    }
+    if (live && k >= kdep) {  // group-uniform
+      // C of lane 0 on every lane of the group (the others add zeros)
+      const double cre = group_sum(c == 0 ? Cre : 0.0), cim = group_sum(c == 0 ? Cim : 0.0);
+      Geom<double> Gk;
+      geometry(d, hRn, q, Gk);
+      const double a = amplitude_re_group(d, n, p, Gk, cre, cim, S, d.t_first + (double)k * h,
+                                          t0, p0q0, w, c);
+      re_a = c == 0 ? a : 0.0;
+    }
+    // deposit: each trajectory's Re a_k goes to LDS (no cross-lane sum per
+    // step); every 64 steps, and at the last, lane j adds the 8 values of
+    // step (k & ~63) + j and flushes them with one coalesced atomic
+    if (c == 0) ring.dep[k & (kWave - 1)][g] = re_a;
+    if ((k & (kWave - 1)) == kWave - 1 || k == N) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int kb = k & ~(kWave - 1);
+      if (lane <= (k & (kWave - 1)) && kb + lane >= kmin) {
+        double tot = 0.0;
+#pragma unroll
+        for (int t = 0; t < kPerWave; ++t) tot += ring.dep[lane][t];
+        if (tot != 0.0) unsafeAtomicAdd(&acc[kb + lane], tot);
+      }
+    }
+    if (k < N && live) {
+      double sx[3], sv[3], xs[3], vs[3], kv[3], K[6];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) K[j] = ring.K[sl][0][j][g];
+      neg_hess_times(K, x, kv);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        sx[a] = v[a];
+        sv[a] = kv[a];
+        xs[a] = x[a] + hh * v[a];
+        vs[a] = v[a] + hh * kv[a];
+      }
+#pragma unroll
+      for (int j = 0; j < 6; ++j) K[j] = ring.K[sl][1][j][g];
+      neg_hess_times(K, xs, kv);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double kx = vs[a];
+        sx[a] += 2.0 * kx;
+        sv[a] += 2.0 * kv[a];
+        xs[a] = x[a] + hh * kx;
+        vs[a] = v[a] + hh * kv[a];
+      }
+#pragma unroll
+      for (int j = 0; j < 6; ++j) K[j] = ring.K[sl][2][j][g];
+      neg_hess_times(K, xs, kv);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double kx = vs[a];
+        sx[a] += 2.0 * kx;
+        sv[a] += 2.0 * kv[a];
+        xs[a] = x[a] + h * kx;
+        vs[a] = v[a] + h * kv[a];
+      }
+#pragma unroll
+      for (int j = 0; j < 6; ++j) K[j] = ring.K[sl][3][j][g];
+      neg_hess_times(K, xs, kv);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        sx[a] += vs[a];
+        sv[a] += kv[a];
+        x[a] = x[a] + h6 * sx[a];
+        v[a] = v[a] + h6 * sv[a];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kPipeThreads)
+propagate_pipe_kernel(const Desc* __restrict__ descs, int n_prob,
+                      const double* __restrict__ field, EnsPtrs e,
+                      const int32_t* __restrict__ dep_from, double* __restrict__ accum) {
+  __shared__ PipeRing ring;
+  int prob;
+  uint32_t unit_pos;
+  if (!find_unit(e, n_prob, blockIdx.x / kPerWave, blockIdx.x % kPerWave, prob, unit_pos)) return;
+  run_pipe_unit(descs, field, e, dep_from, accum, prob, unit_pos, ring);
+}
+
+// Persistent form: a fixed grid of workgroups pulls units (pack queue[u / 8],
+// positions 8 (u % 8) ..) through an atomic counter until all are taken.
+__global__ void __launch_bounds__(kPipeThreads)
+propagate_pipe_persistent(const Desc* __restrict__ descs, int n_prob,
+                          const double* __restrict__ field, EnsPtrs e,
+                          const int32_t* __restrict__ dep_from, double* __restrict__ accum,
+                          const uint32_t* __restrict__ queue, uint32_t* __restrict__ counter) {
+  __shared__ PipeRing ring;
+  __shared__ uint32_t next;
+  const uint32_t total = e.pack_start[n_prob] * (uint32_t)kPerWave;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
+    __syncthreads();
+    const uint32_t u = next;
+    __syncthreads();  // every thread has read `next` before thread 0 rewrites it
+    if (u >= total) break;
+    int prob;
+    uint32_t unit_pos;
+    if (!find_unit(e, n_prob, queue[u / kPerWave], u % kPerWave, prob, unit_pos)) continue;
+    run_pipe_unit(descs, field, e, dep_from, accum, prob, unit_pos, ring);
+  }
+}
+
 template <bool Track>
 __global__ void __launch_bounds__(kWave)
 propagate_latency_kernel(const Desc* __restrict__ descs, int n_prob,
@@ -304,28 +680,6 @@ propagate_latency_kernel(const Desc* __restrict__ descs, int n_prob,
   run_unit<Track>(descs, field, e, dep_from, accum, rec, prob, unit_pos, threadIdx.x);
 }
 
-// Persistent form: a fixed grid pulls units (pack queue[u / 8], positions
-// 8 (u % 8) ..) through an atomic counter until all 8 x (packs) units are
-// taken; every wavefront exits then.
-__global__ void __launch_bounds__(kWave)
-propagate_latency_persistent(const Desc* __restrict__ descs, int n_prob,
-                             const double* __restrict__ field, EnsPtrs e,
-                             const int32_t* __restrict__ dep_from, double* __restrict__ accum,
-                             const uint32_t* __restrict__ queue, uint32_t* __restrict__ counter) {
-  const int lane = threadIdx.x;
-  const uint32_t total = e.pack_start[n_prob] * (uint32_t)kPerWave;
-  for (;;) {
-    uint32_t u = 0;
-    if (lane == 0) u = atomicAdd(counter, 1u);
-    u = __builtin_amdgcn_readfirstlane(u);
-    if (u >= total) break;
-    int prob;
-    uint32_t unit_pos;
-    if (!find_unit(e, n_prob, queue[u / kPerWave], u % kPerWave, prob, unit_pos)) continue;
-    run_unit<false>(descs, field, e, dep_from, accum, Records{}, prob, unit_pos, lane);
-  }
-}
-
 }  // namespace
 
 hipError_t launch_propagate_latency(const Desc* descs, int n_prob, const double* field,
@@ -333,17 +687,17 @@ hipError_t launch_propagate_latency(const Desc* descs, int n_prob, const double*
                                     double* accum, const Records& rec, hipStream_t s,
                                     const LaunchCfg& cfg) {
   if (max_packs == 0) return hipSuccess;
-  if (cfg.persistent && !rec.any()) {
-    hipLaunchKernelGGL(propagate_latency_persistent, dim3(cfg.grid), dim3(kWave), 0, s, descs,
+  const uint32_t units = (uint32_t)((uint64_t)max_packs * kPerWave);
+  if (rec.any()) {  // records: the one-wavefront form
+    hipLaunchKernelGGL(propagate_latency_kernel<true>, dim3(units), dim3(kWave), 0, s, descs,
+                       n_prob, field, e, dep_from, accum, rec);
+  } else if (cfg.persistent) {
+    const uint32_t grid = cfg.grid / 2 > 0 ? cfg.grid / 2 : 1;  // two wavefronts per workgroup
+    hipLaunchKernelGGL(propagate_pipe_persistent, dim3(grid), dim3(kPipeThreads), 0, s, descs,
                        n_prob, field, e, dep_from, accum, cfg.queue, cfg.counter);
   } else {
-    const dim3 grid((uint32_t)((uint64_t)max_packs * kPerWave));
-    if (rec.any())
-      hipLaunchKernelGGL(propagate_latency_kernel<true>, grid, dim3(kWave), 0, s, descs, n_prob,
-                         field, e, dep_from, accum, rec);
-    else
-      hipLaunchKernelGGL(propagate_latency_kernel<false>, grid, dim3(kWave), 0, s, descs, n_prob,
-                         field, e, dep_from, accum, rec);
+    hipLaunchKernelGGL(propagate_pipe_kernel, dim3(units), dim3(kPipeThreads), 0, s, descs,
+                       n_prob, field, e, dep_from, accum);
   }
   return hipGetLastError();
 }

@@ -89,6 +89,34 @@ def test_latency_form_matches_oracle_and_wide_form(sf, orc, case):
     print(f"  final records vs oracle: largest error / bound {worst:.2e}", flush=True)
 
 
+@pytest.mark.parametrize("case", ["h2", "n2pair", "n2cap"])
+def test_pipelined_form_equals_one_wavefront_form(sf, orc, case):
+    """Without records the latency form runs its orbit on a second wavefront
+    a step ahead (pipelined); with records it runs on one wavefront.  Both
+    take the same operations on the same operands: their dipole sums agree to
+    the order of the atomics, and with the oracle to 1e-10."""
+    import torch
+    if case == "h2":
+        probs, n, seeds = [workloads.h2_softcore()], [4096], [1001]
+    elif case == "n2pair":
+        probs, n, seeds = [workloads.n2(0.0), workloads.n2(90.0)], [1500, 1500], [1002, 1002]
+    else:
+        probs, n, seeds = [dict(workloads.n2(0.0), c_max=1e3)], [3000], [1002]
+    print(f"pipelined vs one-wavefront latency form: {case} {n}", flush=True)
+    ens, ws = sf.sample_initial(probs, n, seeds)
+    acc_p, _ = sf.propagate(probs, ens, workspace=ws)                  # pipelined
+    acc_1, _ = sf.propagate(probs, ens, final_state=True, workspace=ws)  # one wavefront
+    torch.cuda.synchronize()
+    acc_p, acc_1 = acc_p.cpu().numpy(), acc_1.cpu().numpy()
+    offs, lens = sf.accum_layout(probs)
+    for P, (p, o, l) in enumerate(zip(probs, offs, lens)):
+        e1 = rel(acc_p[o:o + l], acc_1[o:o + l])
+        acc_o, _, _ = orc.run(p, seeds[P], 0, n[P], NTHREADS)
+        eo = rel(acc_p[o:o + l], acc_o)
+        print(f"  problem {P}: pipelined vs one-wavefront {e1:.2e}, vs oracle {eo:.2e}", flush=True)
+        assert e1 < 1e-13 and eo < 1e-10
+
+
 def test_latency_form_prefactor_cap(sf, orc):
     """The prefactor cap in the latency form: the decision of a group's lane 0
     stops the whole trajectory (dipole sums against the oracle's with the
