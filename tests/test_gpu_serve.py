@@ -83,6 +83,27 @@ def test_served_request_matches_oracle(sf, orc, window, n_groups, window_ms):
     assert rel(r.result["yield"].numpy(), Yo) < 1e-10
 
 
+@pytest.mark.parametrize("window", [500, 2999])
+def test_large_request_in_windows_matches_one_launch(sf, window):
+    """A request of 300,000 trajectories (about 4,700 packs, more wavefronts
+    than the device keeps resident, so every window runs in rounds) served
+    in windows equals the same request run in one launch of the plain kernel
+    and the step-wise path, up to the order of the dipole atomics."""
+    prob, n, seed = workloads.h2_softcore(), 300_000, 1001
+    S = server(window=window, n_groups=1, pool_bytes=2 << 30)
+    print(f"H2 {n} trajectories, windows of {window} steps", flush=True)
+    S.submit("w", prob, n, seed)
+    S.drain()
+    v_win = S.completed[0].result["v"].numpy()
+    S1 = server(window=window, n_groups=1, pool_bytes=2 << 30, window_ms=40.0)
+    S1.submit("one", prob, n, seed)   # alone: one whole-pulse launch
+    S1.drain()
+    v_one = S1.completed[0].result["v"].numpy()
+    assert rel(v_win, v_one) < 1e-13
+    v_st, _, _ = stepwise(sf, prob, n, seed)
+    assert rel(v_win, v_st) < 1e-13
+
+
 def test_served_mix_matches_stepwise_path(sf):
     S = server(window=512)
     reqs = requests()
