@@ -5,6 +5,7 @@ of the benchmark use it; the product path never imports it.  Problems are
 the plain dictionaries of the ``workloads`` module.
 """
 import ctypes as C
+import math
 import os
 
 import numpy as np
@@ -314,6 +315,33 @@ def spectrum(v, t_first, dt, tau_H, omega):
     lib().orc_spectrum(_dp(v), v.size, float(t_first), float(dt), float(tau_H), _dp(om),
                        om.size, _dp(Vr), _dp(Vi), _dp(Y))
     return Vr + 1j * Vi, Y
+
+
+def fft_log2_len(n_t):
+    """log2 of the zero-padded transform length: the power of two >= 8 n_t."""
+    return int(math.ceil(math.log2(8 * max(int(n_t), 1))))
+
+
+def spectrum_fft(v, t_first, dt, tau_H, log2_len=None):
+    """Eq. 3 on the grid of a zero-padded transform: x_k = v_k W_H(t_k)
+    (k < n_t; 0 up to L = 2^log2_len), w_j = 2 pi j / (L dt) for
+    j = 0 .. L/2, V_j = dt sum_k x_k exp(i w_j t_k) with t_k = t_first + k dt;
+    the dipole acceleration's spectrum A = -i w V (Sec. II.A: the forms
+    differ by that factor), yield |A|^2 = w^2 |V|^2 and phase arg A.  numpy's
+    FFT is the transform step.  Returns (omega, V, yield, phase)."""
+    v = _arr(v)
+    n = v.size
+    L = 1 << (fft_log2_len(n) if log2_len is None else int(log2_len))
+    t = t_first + np.arange(n) * dt
+    wh = np.where(np.abs(t) <= tau_H, 0.5 * (1.0 + np.cos(np.pi * t / tau_H)), 0.0)
+    x = np.zeros(L)
+    x[:n] = v * wh
+    X = np.fft.ifft(x) * L                      # sum_k x_k exp(+2 pi i j k / L)
+    j = np.arange(L // 2 + 1)
+    w = 2.0 * np.pi * j / (L * dt)
+    V = dt * np.exp(1j * w * t_first) * X[:L // 2 + 1]
+    A = -1j * w * V
+    return w, V, np.abs(A) ** 2, np.angle(A)
 
 
 def gabor(v, t_first, dt, sigma, t_c, omega):

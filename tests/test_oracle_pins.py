@@ -694,3 +694,43 @@ def test_averaging_quadrature_integrates_the_isotropic_density():
         exact = 1.0 / (k + 1)  # (1/2) int_{-1}^{1} x^k dx
         assert abs(sum(w * x ** k for w, x in zip(wts, xs)) - exact) < 1e-14
     assert av["joint"]["align"] == {"kind": "cos2m", "theta": 0.0, "phi": 0.0, "m": 0}
+
+
+# ------------------------------------------------- spectrum on the FFT grid
+def _fft_case(n=1000, seed=3):
+    rng = np.random.default_rng(seed)
+    dt, t_first = 0.1, -0.5 * (n - 1) * 0.1
+    t = t_first + np.arange(n) * dt
+    v = rng.normal(size=n) * 0.1 + np.cos(0.057 * 7 * t) + 0.3 * np.sin(0.057 * 13 * t + 0.4)
+    return v, t_first, dt, 0.5 * n * dt
+
+
+def test_fft_spectrum_equals_direct_transform(orc):
+    """Eq. 3 on the FFT grid equals the direct sum (itself pinned by closed
+    forms) at the same frequencies, for bins across the whole grid."""
+    v, t_first, dt, tau_H = _fft_case()
+    w, V, Y, ph = orc.spectrum_fft(v, t_first, dt, tau_H)
+    L = 2 * (w.size - 1)
+    assert L == 1 << orc.fft_log2_len(v.size) and L >= 8 * v.size
+    j = np.array([0, 1, 2, 17, 333, 1234, L // 4, L // 2 - 1, L // 2])
+    Vd, Yd = orc.spectrum(v, t_first, dt, tau_H, w[j])
+    assert np.max(np.abs(V[j] - Vd)) < 1e-12 * np.max(np.abs(Vd))
+    assert np.allclose(Y[j], Yd, rtol=1e-10, atol=1e-14 * Yd.max())
+    # A = -i w V: |A|^2 is the yield, its phase is arg V - pi/2 (w > 0)
+    sel = j[1:]
+    d = np.angle(np.exp(1j * (ph[sel] - np.angle(V[sel]) + np.pi / 2)))
+    assert np.max(np.abs(d)) < 1e-12
+
+
+def test_fft_spectrum_parseval_and_padding(orc):
+    """Parseval for the real windowed signal, and twice the padding puts the
+    same values on every second bin (the time origin t_first is kept)."""
+    v, t_first, dt, tau_H = _fft_case(777, 5)
+    w, V, Y, _ = orc.spectrum_fft(v, t_first, dt, tau_H)
+    L = 2 * (w.size - 1)
+    t = t_first + np.arange(v.size) * dt
+    x = v * np.where(np.abs(t) <= tau_H, 0.5 * (1 + np.cos(np.pi * t / tau_H)), 0.0)
+    X2 = np.abs(V / dt) ** 2
+    assert abs((X2[0] + 2 * X2[1:-1].sum() + X2[-1]) / L - np.sum(x * x)) < 1e-10 * np.sum(x * x)
+    w2, V2, _, _ = orc.spectrum_fft(v, t_first, dt, tau_H, orc.fft_log2_len(v.size) + 1)
+    assert np.allclose(w2[::2], w) and np.max(np.abs(V2[::2] - V)) < 1e-12 * np.abs(V).max()
