@@ -648,7 +648,9 @@ def main():
         e1.record(stream)
         sf.dipole(probs, acc, n_traj, v_out=v)
         for (t0, tauh, om), o, l in zip(grids, offs, lens):
+            # Eq. 3 on the harmonic grid and on the zero-padded FFT grid
             sf.spectrum(v[o:o + l], t0, probs[0]["dt"], tauh, om)
+            sf.spectrum_fft(v[o:o + l], t0, probs[0]["dt"], tauh)
         if timed:
             prop_ms.append((e0, e1))
 

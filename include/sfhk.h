@@ -285,6 +285,34 @@ sfhk_status sfhk_spectrum(const double* v, int32_t n_t, double t_first, double d
                           const double* omega, int32_t n_omega, double* V_re, double* V_im,
                           double* yield, void* stream);
 
+/* Host only.  log2 of the default zero-padded transform length for n_t
+ * samples: the power of two >= 8 n_t (0 for n_t < 1 or n_t > 2^25). */
+int32_t sfhk_fft_log2_len(int32_t n_t);
+
+/* Host only.  Device work bytes of sfhk_spectrum_fft at length 2^log2_len
+ * (two complex double arrays of that length; 0 outside 1..28). */
+size_t sfhk_spectrum_fft_work_bytes(int32_t log2_len);
+
+/* Eq. 3 on the grid of a zero-padded FFT: the windowed dipole
+ * x_k = v_k W_H(t_k) (W_H as for sfhk_spectrum; k < n_t, zeros up to
+ * L = 2^log2_len), radix-2 passes of the transform with the positive
+ * exponent, and for j = 0 .. L/2, w_j = 2 pi j / (L dt):
+ * V_j = dt exp(i w_j t_first) sum_k x_k exp(2 pi i j k / L)
+ *     = dt sum_k x_k exp(i w_j t_k),
+ * the dipole acceleration's spectrum A_j = -i w_j V_j (Sec. II.A: the two
+ * forms differ by that factor), yield_j = |A_j|^2 = w_j^2 |V_j|^2 and
+ * phase_j = arg A_j.
+ *   v: device [n_t]; log2_len: 1..28 with 2^log2_len >= n_t
+ *   (sfhk_fft_log2_len gives the default); work: device, >=
+ *   sfhk_spectrum_fft_work_bytes(log2_len) bytes, overwritten;
+ *   V_re, V_im, yield: device [L/2 + 1]; phase: device [L/2 + 1] or NULL.
+ * Errors: SFHK_E_INVALID for bad sizes or pointers, SFHK_E_NOMEM for a
+ * small work buffer, before anything is enqueued. */
+sfhk_status sfhk_spectrum_fft(const double* v, int32_t n_t, double t_first, double dt,
+                              double tau_H, int32_t log2_len, void* work, size_t work_bytes,
+                              double* V_re, double* V_im, double* yield, double* phase,
+                              void* stream);
+
 /* Classical returns of a sampled ensemble (Sec. III.C: long and short
  * trajectories born in successive half-cycles return in the same window):
  * for every live slot the first step k > k0 at which |q_k| < r_return after

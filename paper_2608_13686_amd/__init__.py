@@ -203,6 +203,31 @@ def spectrum(v, t_first, dt, tau_H, omega, stream=None):
 
 
 @_on_stream
+def spectrum_fft(v, t_first, dt, tau_H, log2_len=None, stream=None):
+    """Eq. 3 on the grid w_j = 2 pi j / (L dt), j = 0 .. L/2, of a transform
+    zero-padded to L = 2^log2_len (default: the power of two >= 8 n_t)
+    (sfhk_spectrum_fft).  Returns (omega, V complex128, yield |A|^2, phase
+    arg A) with A = -i w V the dipole acceleration's spectrum."""
+    v = v.contiguous()
+    n = v.numel()
+    L_ = _abi.lib()
+    b = L_.sfhk_fft_log2_len(n) if log2_len is None else int(log2_len)
+    nb = L_.sfhk_spectrum_fft_work_bytes(b)
+    if nb == 0:
+        raise SfhkError(1, "sfhk_spectrum_fft_work_bytes")
+    work = torch.empty(nb, dtype=torch.uint8, device=v.device)
+    m = (1 << b) // 2 + 1
+    Vr = torch.empty(m, dtype=torch.float64, device=v.device)
+    Vi, Y, ph = torch.empty_like(Vr), torch.empty_like(Vr), torch.empty_like(Vr)
+    _abi.check(L_.sfhk_spectrum_fft(
+        C.c_void_p(v.data_ptr()), n, float(t_first), float(dt), float(tau_H), b,
+        C.c_void_p(work.data_ptr()), nb, C.c_void_p(Vr.data_ptr()), C.c_void_p(Vi.data_ptr()),
+        C.c_void_p(Y.data_ptr()), C.c_void_p(ph.data_ptr()), _stream(stream)), "sfhk_spectrum_fft")
+    omega = 2.0 * math.pi * torch.arange(m, dtype=torch.float64, device=v.device) / ((1 << b) * dt)
+    return omega, torch.complex(Vr, Vi), Y, ph
+
+
+@_on_stream
 def return_steps(probs, ens, r_return=4.0, workspace=None, stream=None):
     """(k_ret int32, e_ret) per slot: first return step into |q| < r_return
     (-1 if none) and the kinetic energy there (sfhk_return_steps)."""

@@ -663,6 +663,39 @@ sfhk_status sfhk_spectrum(const double* v, int32_t n_t, double t_first, double d
   return ok();
 }
 
+int32_t sfhk_fft_log2_len(int32_t n_t) {
+  if (n_t < 1 || n_t > (1 << 25)) return 0;
+  int32_t b = 0;
+  while ((int64_t(1) << b) < 8 * (int64_t)n_t) ++b;
+  return b;
+}
+
+size_t sfhk_spectrum_fft_work_bytes(int32_t log2_len) {
+  if (log2_len < 1 || log2_len > 28) return 0;
+  return sizeof(double) * 4 * ((size_t)1 << log2_len);  // two complex arrays of L
+}
+
+sfhk_status sfhk_spectrum_fft(const double* v, int32_t n_t, double t_first, double dt,
+                              double tau_H, int32_t log2_len, void* work, size_t work_bytes,
+                              double* V_re, double* V_im, double* yield, double* phase,
+                              void* stream) {
+  if (n_t < 1) return fail(SFHK_E_INVALID, "n_t must be >= 1");
+  if (log2_len < 1 || log2_len > 28 || (int64_t(1) << log2_len) < (int64_t)n_t)
+    return fail(SFHK_E_INVALID, "log2_len must be in 1..28 with 2^log2_len >= n_t");
+  if (!(is_finite(t_first) && is_finite(dt) && dt > 0 && is_finite(tau_H) && tau_H > 0))
+    return fail(SFHK_E_INVALID, "t_first, dt > 0 and tau_H > 0 must be finite");
+  if (!v || !work || !V_re || !V_im || !yield)
+    return fail(SFHK_E_INVALID, "spectrum pointers must be non-null (phase may be)");
+  const size_t need = sfhk_spectrum_fft_work_bytes(log2_len);
+  if (work_bytes < need)
+    return fail(SFHK_E_NOMEM, "work has %zu bytes, needs %zu", work_bytes, need);
+  hipError_t e = launch_spectrum_fft(v, n_t, t_first, dt, tau_H, log2_len,
+                                     static_cast<double2*>(work), V_re, V_im, yield, phase,
+                                     static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "spectrum fft");
+  return ok();
+}
+
 sfhk_status sfhk_return_steps(const sfhk_problem* probs, int32_t n_prob,
                               const sfhk_ensemble* ens, double r_return, int32_t* k_ret,
                               double* e_ret, void* workspace, size_t workspace_bytes,

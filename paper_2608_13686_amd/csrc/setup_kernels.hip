@@ -644,6 +644,79 @@ hipError_t launch_spectrum(const double* v, int n_t, double t_first, double dt, 
   return hipGetLastError();
 }
 
+// ------------------------------------------------ spectrum on an FFT grid
+// Eq. 3 on the grid w_j = 2 pi j / (L dt) of a zero-padded transform of
+// length L = 2^log2_len: the windowed dipole x_k = v_k W_H(t_k) is loaded
+// into a complex array (zeros past n_t), transformed by log2_len radix-2
+// Stockham passes with the positive exponent (X_j = sum_k x_k
+// exp(2 pi i j k / L); out of place, so no bit reversal), and
+// V_j = dt exp(i w_j t_first) X_j, A = -i w V, yield |A|^2 and phase arg A
+// are formed for j = 0 .. L/2.  Twiddles come from sincospi of the exact
+// rational k / Ns.
+__global__ void fft_load_kernel(const double* __restrict__ v, int n_t, double t_first, double dt,
+                                double tau_H, uint32_t L, double2* __restrict__ a) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= L) return;
+  double x = 0.0;
+  if ((int)k < n_t) {
+    const double t = t_first + (double)k * dt;
+    const double wh = fabs(t) <= tau_H ? 0.5 * (1.0 + cos(kPi * t / tau_H)) : 0.0;
+    x = v[k] * wh;
+  }
+  a[k] = make_double2(x, 0.0);
+}
+
+__global__ void fft_stage_kernel(const double2* __restrict__ in, double2* __restrict__ out,
+                                 uint32_t L, uint32_t Ns) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t half = L >> 1;
+  if (j >= half) return;
+  const uint32_t k = j & (Ns - 1);  // Ns is a power of two
+  const double2 a0 = in[j], b = in[j + half];
+  double sn, cs;
+  sincospi((double)k / (double)Ns, &sn, &cs);
+  const double2 a1 = make_double2(b.x * cs - b.y * sn, b.x * sn + b.y * cs);
+  const uint32_t o = ((j - k) << 1) + k;
+  out[o] = make_double2(a0.x + a1.x, a0.y + a1.y);
+  out[o + Ns] = make_double2(a0.x - a1.x, a0.y - a1.y);
+}
+
+__global__ void fft_post_kernel(const double2* __restrict__ X, uint32_t L, double t_first,
+                                double dt, double* __restrict__ V_re, double* __restrict__ V_im,
+                                double* __restrict__ yield, double* __restrict__ phase) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > (L >> 1)) return;
+  const double w = 2.0 * kPi * (double)j / ((double)L * dt);
+  double sn, cs;
+  sincos(w * t_first, &sn, &cs);
+  const double2 x = X[j];
+  const double vr = dt * (cs * x.x - sn * x.y), vi = dt * (sn * x.x + cs * x.y);
+  V_re[j] = vr;
+  V_im[j] = vi;
+  yield[j] = w * w * (vr * vr + vi * vi);
+  if (phase) phase[j] = atan2(-w * vr, w * vi);  // arg of A = -i w V = w vi - i w vr
+}
+
+hipError_t launch_spectrum_fft(const double* v, int n_t, double t_first, double dt, double tau_H,
+                               int log2_len, double2* work, double* V_re, double* V_im,
+                               double* yield, double* phase, hipStream_t s) {
+  const uint32_t L = 1u << log2_len;
+  double2* a = work;
+  double2* b = work + L;
+  hipLaunchKernelGGL(fft_load_kernel, dim3(blocks_for(L, kBlock)), dim3(kBlock), 0, s, v, n_t,
+                     t_first, dt, tau_H, L, a);
+  for (uint32_t Ns = 1; Ns < L; Ns <<= 1) {
+    hipLaunchKernelGGL(fft_stage_kernel, dim3(blocks_for(L / 2, kBlock)), dim3(kBlock), 0, s, a,
+                       b, L, Ns);
+    double2* t = a;
+    a = b;
+    b = t;
+  }
+  hipLaunchKernelGGL(fft_post_kernel, dim3(blocks_for(L / 2 + 1, kBlock)), dim3(kBlock), 0, s, a,
+                     L, t_first, dt, V_re, V_im, yield, phase);
+  return hipGetLastError();
+}
+
 }  // namespace sfhk
 
 namespace sfhk {

@@ -154,6 +154,12 @@ hipError_t launch_gabor(const double* v, int n_t, double t_first, double dt, dou
 hipError_t launch_spectrum(const double* v, int n_t, double t_first, double dt, double tau_H,
                            const double* omega, int n_omega, double* V_re, double* V_im,
                            double* yield, hipStream_t s);
+// Eq. 3 on the grid of a zero-padded transform of length 2^log2_len (work:
+// 2^(log2_len + 1) complex doubles); outputs [2^(log2_len - 1) + 1], phase
+// nullable.
+hipError_t launch_spectrum_fft(const double* v, int n_t, double t_first, double dt, double tau_H,
+                               int log2_len, double2* work, double* V_re, double* V_im,
+                               double* yield, double* phase, hipStream_t s);
 // propagate_f64.hip, propagate_mixed.hip
 // Launch form of the trajectory kernels: one wavefront per pack (grid =
 // max_packs), or a persistent grid pulling packs from queue[] through an

@@ -204,6 +204,25 @@ def test_gabor_arguments_validated(L):
     assert lib.sfhk_gabor(*args(n_w=0)) == 0
 
 
+def test_fft_spectrum_sizes_and_validation(L):
+    lib = L.lib()
+    # the power of two >= 8 n_t; work = two complex double arrays of that length
+    assert [lib.sfhk_fft_log2_len(n) for n in (1, 2, 3, 13239, 3311)] == [3, 4, 5, 17, 15]
+    assert lib.sfhk_fft_log2_len(0) == 0 and lib.sfhk_fft_log2_len(1 << 26) == 0
+    assert lib.sfhk_spectrum_fft_work_bytes(17) == 32 << 17
+    assert lib.sfhk_spectrum_fft_work_bytes(0) == 0 and lib.sfhk_spectrum_fft_work_bytes(29) == 0
+    fake = C.c_void_p(64)  # never dereferenced: every call below fails before enqueueing
+    args = lambda n_t=100, b=10, dt=0.1, work=fake, nb=32 << 10, ptr=fake: (
+        ptr, n_t, -5.0, dt, 4.0, b, work, nb, ptr, ptr, ptr, None, None)
+    assert lib.sfhk_spectrum_fft(*args(n_t=0)) == 1
+    assert lib.sfhk_spectrum_fft(*args(b=6)) == 1       # 64 < n_t
+    assert lib.sfhk_spectrum_fft(*args(b=29)) == 1
+    assert lib.sfhk_spectrum_fft(*args(dt=0.0)) == 1
+    assert lib.sfhk_spectrum_fft(*args(ptr=None)) == 1
+    assert lib.sfhk_spectrum_fft(*args(work=None)) == 1
+    assert lib.sfhk_spectrum_fft(*args(nb=(32 << 10) - 1)) == 2
+
+
 def test_missing_library_fails_loudly(monkeypatch):
     """Without the built library every step raises: the product path has no
     CPU fallback."""

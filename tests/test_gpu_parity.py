@@ -391,6 +391,45 @@ def test_spectrum_matches_oracle(sf, orc):
     assert rel_l2(Y.cpu().numpy(), Yo) < 1e-12
 
 
+@pytest.mark.parametrize("case", ["h2_random", "n2_dipole", "pow2", "longer", "one"])
+def test_fft_spectrum_matches_oracle(sf, orc, case):
+    """Eq. 3 on the zero-padded FFT grid (sfhk_spectrum_fft) against the
+    oracle's (numpy's FFT, pinned to the direct transform): V, the
+    acceleration yield and its phase, at the default length (the power of
+    two >= 8 n_t), a longer one, n_t a power of two and n_t = 1."""
+    import torch
+    rng = np.random.default_rng(11)
+    log2 = None
+    if case in ("h2_random", "longer"):
+        p = workloads.h2_softcore()
+        N, t0, tau = sf.problem_steps(p)
+        v = rng.normal(size=N + 1)
+        dt = p["dt"]
+        log2 = 17 if case == "longer" else None
+    elif case == "n2_dipole":
+        p = workloads.n2(0.0)
+        N, t0, tau = sf.problem_steps(p)
+        v, _, _ = orc.dipole(p, 1002, 0, 400, NTHREADS)
+        dt = p["dt"]
+    elif case == "pow2":
+        v, t0, dt, tau = rng.normal(size=4096), -204.8, 0.1, 409.6
+    else:
+        v, t0, dt, tau = np.array([0.7]), 0.0, 0.1, 1.0
+    print(f"FFT spectrum {case}: n_t {len(v)}, log2_len {log2}", flush=True)
+    w, V, Y, ph = sf.spectrum_fft(torch.tensor(v, device="cuda"), t0, dt, tau / 2, log2)
+    torch.cuda.synchronize()
+    wo, Vo, Yo, pho = orc.spectrum_fft(v, t0, dt, tau / 2, log2)
+    assert w.numel() == wo.size and np.allclose(w.cpu().numpy(), wo, rtol=1e-15, atol=0)
+    V, Y, ph = V.cpu().numpy(), Y.cpu().numpy(), ph.cpu().numpy()
+    assert rel_l2(V, Vo) < 1e-12
+    assert rel_l2(Y, Yo) < 1e-12
+    # the phase where the yield is not negligible (arg of ~0 is arbitrary)
+    sel = Yo > 1e-12 * Yo.max()   # |A| > 1e-6 max|A|: phase error < ~1e-7
+    sel[0] = False
+    dph = np.angle(np.exp(1j * (ph[sel] - pho[sel])))
+    assert np.max(np.abs(dph)) < 1e-6
+
+
 def test_whole_path_spectrum_h2(sf, orc):
     """Dipole and harmonic spectrum of the H2 workload (harmonics 0..40)."""
     p = workloads.h2_softcore()
