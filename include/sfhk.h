@@ -47,7 +47,7 @@ typedef enum {
   SFHK_E_NOMEM = 2,       /* workspace or buffer too small                 */
   SFHK_E_DEVICE = 3,      /* HIP reported an error                          */
   SFHK_E_BUSY = 4,        /* resource in use                                */
-  SFHK_E_UNSUPPORTED = 5  /* valid request this build does not implement    */
+  SFHK_E_UNSUPPORTED = 5  /* valid request the library does not implement   */
 } sfhk_status;
 
 typedef enum { SFHK_FP64 = 0, SFHK_MIXED = 1 } sfhk_precision;

@@ -9,7 +9,7 @@ form), and caches the choice as JSON per (GPU architecture, precision,
 potential kinds, GTO primitives).  Trajectories per lane is fixed at 1: the
 FP64 state of one trajectory already fills the register budget of two
 wavefronts per SIMD, and two FP32 trajectories per lane would pay only
-through packed FP32 arithmetic, which this build does not emit.
+through packed FP32 arithmetic, which the library does not emit.
 
     python -m paper_2608_13686_amd.autotune --workload batched
 """
