@@ -344,6 +344,26 @@ def spectrum_fft(v, t_first, dt, tau_H, log2_len=None):
     return w, V, np.abs(A) ** 2, np.angle(A)
 
 
+def acceleration_fft(v, t_first, dt, tau_H, log2_len=None):
+    """The dipole acceleration on the step grid: the time derivative of the
+    windowed dipole W_H v through its zero-padded spectrum (A = -i w V,
+    Sec. II.A), a_k = (1/L) sum_j (-i w_j) X_j exp(-2 pi i j k / L) with the
+    two-sided frequencies w_j = 2 pi j / (L dt) (j < L/2), 2 pi (j - L) / (L dt)
+    (j > L/2) and the Nyquist term dropped; k < n_t.  numpy's FFT is the
+    transform step."""
+    v = _arr(v)
+    n = v.size
+    L = 1 << (fft_log2_len(n) if log2_len is None else int(log2_len))
+    t = t_first + np.arange(n) * dt
+    wh = np.where(np.abs(t) <= tau_H, 0.5 * (1.0 + np.cos(np.pi * t / tau_H)), 0.0)
+    x = np.zeros(L)
+    x[:n] = v * wh
+    X = np.fft.ifft(x) * L
+    w = 2.0 * np.pi * np.fft.fftfreq(L, d=dt)
+    w[L // 2] = 0.0
+    return (np.fft.fft(-1j * w * X) / L).real[:n]
+
+
 def gabor(v, t_first, dt, sigma, t_c, omega):
     """(G [n_c, n_omega] complex, yield) of the Gaussian-window transform."""
     v, tc, om = _arr(v), _arr(t_c), _arr(omega)
