@@ -313,6 +313,19 @@ sfhk_status sfhk_spectrum_fft(const double* v, int32_t n_t, double t_first, doub
                               double* V_re, double* V_im, double* yield, double* phase,
                               void* stream);
 
+/* The dipole acceleration on the step grid (Sec. II.A: the acceleration
+ * form of the dipole, whose spectrum is A = -i w V): the time derivative of
+ * the windowed dipole x_k = v_k W_H(t_k) taken in the spectrum of the same
+ * zero-padded transform as sfhk_spectrum_fft,
+ * a_k = (1/L) sum_j (-i w_j) X_j exp(-2 pi i j k / L), k < n_t, with the
+ * two-sided frequencies w_j = 2 pi j / (L dt) for j < L/2 and
+ * 2 pi (j - L) / (L dt) for j > L/2 (the Nyquist term is dropped).
+ *   v, a: device [n_t]; log2_len, work: as for sfhk_spectrum_fft.
+ * Errors as for sfhk_spectrum_fft. */
+sfhk_status sfhk_acceleration(const double* v, int32_t n_t, double t_first, double dt,
+                              double tau_H, int32_t log2_len, void* work, size_t work_bytes,
+                              double* a, void* stream);
+
 /* Classical returns of a sampled ensemble (Sec. III.C: long and short
  * trajectories born in successive half-cycles return in the same window):
  * for every live slot the first step k > k0 at which |q_k| < r_return after

@@ -228,6 +228,26 @@ def spectrum_fft(v, t_first, dt, tau_H, log2_len=None, stream=None):
 
 
 @_on_stream
+def acceleration(v, t_first, dt, tau_H, log2_len=None, stream=None):
+    """The dipole acceleration on the step grid: the time derivative of the
+    windowed dipole through its zero-padded spectrum (sfhk_acceleration)."""
+    v = v.contiguous()
+    n = v.numel()
+    L_ = _abi.lib()
+    b = L_.sfhk_fft_log2_len(n) if log2_len is None else int(log2_len)
+    nb = L_.sfhk_spectrum_fft_work_bytes(b)
+    if nb == 0:
+        raise SfhkError(1, "sfhk_spectrum_fft_work_bytes")
+    work = torch.empty(nb, dtype=torch.uint8, device=v.device)
+    a = torch.empty(n, dtype=torch.float64, device=v.device)
+    _abi.check(L_.sfhk_acceleration(
+        C.c_void_p(v.data_ptr()), n, float(t_first), float(dt), float(tau_H), b,
+        C.c_void_p(work.data_ptr()), nb, C.c_void_p(a.data_ptr()), _stream(stream)),
+        "sfhk_acceleration")
+    return a
+
+
+@_on_stream
 def return_steps(probs, ens, r_return=4.0, workspace=None, stream=None):
     """(k_ret int32, e_ret) per slot: first return step into |q| < r_return
     (-1 if none) and the kinetic energy there (sfhk_return_steps)."""

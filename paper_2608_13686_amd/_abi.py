@@ -20,7 +20,8 @@ EXPORTS = ["sfhk_abi_version", "sfhk_last_error", "sfhk_problem_steps", "sfhk_wo
            "sfhk_plan_replay", "sfhk_plan_destroy", "sfhk_plan_kernel_ms", "sfhk_request_bytes", "sfhk_request_layout",
            "sfhk_request_table_bytes", "sfhk_request_init", "sfhk_serve_window",
            "sfhk_request_run", "sfhk_request_finalize", "sfhk_gabor", "sfhk_return_steps",
-           "sfhk_fft_log2_len", "sfhk_spectrum_fft_work_bytes", "sfhk_spectrum_fft"]
+           "sfhk_fft_log2_len", "sfhk_spectrum_fft_work_bytes", "sfhk_spectrum_fft",
+           "sfhk_acceleration"]
 
 
 class Center(C.Structure):
@@ -119,6 +120,9 @@ def lib():
                                         C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p, C.c_void_p]
         L.sfhk_spectrum_fft.restype = C.c_int
+        L.sfhk_acceleration.argtypes = [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double,
+                                        C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]
+        L.sfhk_acceleration.restype = C.c_int
         L.sfhk_plan_workspace_bytes.argtypes = [P, C.c_int32, u64p]
         L.sfhk_plan_workspace_bytes.restype = C.c_size_t
         L.sfhk_plan_create.argtypes = [P, C.c_int32, u64p, u64p, u64p, C.c_int32,

@@ -696,6 +696,25 @@ sfhk_status sfhk_spectrum_fft(const double* v, int32_t n_t, double t_first, doub
   return ok();
 }
 
+sfhk_status sfhk_acceleration(const double* v, int32_t n_t, double t_first, double dt,
+                              double tau_H, int32_t log2_len, void* work, size_t work_bytes,
+                              double* a, void* stream) {
+  if (n_t < 1) return fail(SFHK_E_INVALID, "n_t must be >= 1");
+  if (log2_len < 1 || log2_len > 28 || (int64_t(1) << log2_len) < (int64_t)n_t)
+    return fail(SFHK_E_INVALID, "log2_len must be in 1..28 with 2^log2_len >= n_t");
+  if (!(is_finite(t_first) && is_finite(dt) && dt > 0 && is_finite(tau_H) && tau_H > 0))
+    return fail(SFHK_E_INVALID, "t_first, dt > 0 and tau_H > 0 must be finite");
+  if (!v || !work || !a) return fail(SFHK_E_INVALID, "v, work and a must be non-null");
+  const size_t need = sfhk_spectrum_fft_work_bytes(log2_len);
+  if (work_bytes < need)
+    return fail(SFHK_E_NOMEM, "work has %zu bytes, needs %zu", work_bytes, need);
+  hipError_t e = launch_acceleration_fft(v, n_t, t_first, dt, tau_H, log2_len,
+                                         static_cast<double2*>(work), a,
+                                         static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "acceleration");
+  return ok();
+}
+
 sfhk_status sfhk_return_steps(const sfhk_problem* probs, int32_t n_prob,
                               const sfhk_ensemble* ens, double r_return, int32_t* k_ret,
                               double* e_ret, void* workspace, size_t workspace_bytes,

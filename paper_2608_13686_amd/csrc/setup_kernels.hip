@@ -667,7 +667,7 @@ __global__ void fft_load_kernel(const double* __restrict__ v, int n_t, double t_
 }
 
 __global__ void fft_stage_kernel(const double2* __restrict__ in, double2* __restrict__ out,
-                                 uint32_t L, uint32_t Ns) {
+                                 uint32_t L, uint32_t Ns, double sign) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t half = L >> 1;
   if (j >= half) return;
@@ -675,6 +675,7 @@ __global__ void fft_stage_kernel(const double2* __restrict__ in, double2* __rest
   const double2 a0 = in[j], b = in[j + half];
   double sn, cs;
   sincospi((double)k / (double)Ns, &sn, &cs);
+  sn *= sign;  // exp(sign i pi k / Ns)
   const double2 a1 = make_double2(b.x * cs - b.y * sn, b.x * sn + b.y * cs);
   const uint32_t o = ((j - k) << 1) + k;
   out[o] = make_double2(a0.x + a1.x, a0.y + a1.y);
@@ -697,23 +698,60 @@ __global__ void fft_post_kernel(const double2* __restrict__ X, uint32_t L, doubl
   if (phase) phase[j] = atan2(-w * vr, w * vi);  // arg of A = -i w V = w vi - i w vr
 }
 
-hipError_t launch_spectrum_fft(const double* v, int n_t, double t_first, double dt, double tau_H,
-                               int log2_len, double2* work, double* V_re, double* V_im,
-                               double* yield, double* phase, hipStream_t s) {
-  const uint32_t L = 1u << log2_len;
-  double2* a = work;
-  double2* b = work + L;
-  hipLaunchKernelGGL(fft_load_kernel, dim3(blocks_for(L, kBlock)), dim3(kBlock), 0, s, v, n_t,
-                     t_first, dt, tau_H, L, a);
+// The derivative in the spectrum: X_j <- -i w_j X_j with the two-sided
+// frequencies (j > L/2 negative) and the Nyquist term dropped.
+__global__ void fft_derivative_kernel(double2* __restrict__ X, uint32_t L, double dt) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= L) return;
+  const double m = j < (L >> 1) ? (double)j : (j == (L >> 1) ? 0.0 : (double)j - (double)L);
+  const double w = 2.0 * kPi * m / ((double)L * dt);
+  const double2 x = X[j];
+  X[j] = make_double2(w * x.y, -w * x.x);  // -i w (x.x + i x.y)
+}
+
+__global__ void fft_real_out_kernel(const double2* __restrict__ y, int n_t, double scale,
+                                    double* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n_t) out[k] = scale * y[k].x;
+}
+
+// log2(L) radix-2 passes between a and b; returns the array holding the result
+static double2* fft_passes(double2* a, double2* b, uint32_t L, double sign, hipStream_t s) {
   for (uint32_t Ns = 1; Ns < L; Ns <<= 1) {
     hipLaunchKernelGGL(fft_stage_kernel, dim3(blocks_for(L / 2, kBlock)), dim3(kBlock), 0, s, a,
-                       b, L, Ns);
+                       b, L, Ns, sign);
     double2* t = a;
     a = b;
     b = t;
   }
-  hipLaunchKernelGGL(fft_post_kernel, dim3(blocks_for(L / 2 + 1, kBlock)), dim3(kBlock), 0, s, a,
+  return a;
+}
+
+hipError_t launch_spectrum_fft(const double* v, int n_t, double t_first, double dt, double tau_H,
+                               int log2_len, double2* work, double* V_re, double* V_im,
+                               double* yield, double* phase, hipStream_t s) {
+  const uint32_t L = 1u << log2_len;
+  hipLaunchKernelGGL(fft_load_kernel, dim3(blocks_for(L, kBlock)), dim3(kBlock), 0, s, v, n_t,
+                     t_first, dt, tau_H, L, work);
+  double2* X = fft_passes(work, work + L, L, 1.0, s);
+  hipLaunchKernelGGL(fft_post_kernel, dim3(blocks_for(L / 2 + 1, kBlock)), dim3(kBlock), 0, s, X,
                      L, t_first, dt, V_re, V_im, yield, phase);
+  return hipGetLastError();
+}
+
+hipError_t launch_acceleration_fft(const double* v, int n_t, double t_first, double dt,
+                                   double tau_H, int log2_len, double2* work, double* a,
+                                   hipStream_t s) {
+  const uint32_t L = 1u << log2_len;
+  hipLaunchKernelGGL(fft_load_kernel, dim3(blocks_for(L, kBlock)), dim3(kBlock), 0, s, v, n_t,
+                     t_first, dt, tau_H, L, work);
+  double2* X = fft_passes(work, work + L, L, 1.0, s);
+  hipLaunchKernelGGL(fft_derivative_kernel, dim3(blocks_for(L, kBlock)), dim3(kBlock), 0, s, X, L,
+                     dt);
+  double2* other = X == work ? work + L : work;
+  double2* y = fft_passes(X, other, L, -1.0, s);
+  hipLaunchKernelGGL(fft_real_out_kernel, dim3(blocks_for((uint64_t)n_t, kBlock)), dim3(kBlock), 0,
+                     s, y, n_t, 1.0 / (double)L, a);
   return hipGetLastError();
 }
 

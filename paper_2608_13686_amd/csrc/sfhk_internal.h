@@ -160,6 +160,11 @@ hipError_t launch_spectrum(const double* v, int n_t, double t_first, double dt, 
 hipError_t launch_spectrum_fft(const double* v, int n_t, double t_first, double dt, double tau_H,
                                int log2_len, double2* work, double* V_re, double* V_im,
                                double* yield, double* phase, hipStream_t s);
+// The dipole acceleration on the step grid: the derivative of the windowed
+// dipole through the same transform, back-transformed; a: [n_t].
+hipError_t launch_acceleration_fft(const double* v, int n_t, double t_first, double dt,
+                                   double tau_H, int log2_len, double2* work, double* a,
+                                   hipStream_t s);
 // propagate_f64.hip, propagate_mixed.hip
 // Launch form of the trajectory kernels: one wavefront per pack (grid =
 // max_packs), or a persistent grid pulling packs from queue[] through an

@@ -221,6 +221,12 @@ def test_fft_spectrum_sizes_and_validation(L):
     assert lib.sfhk_spectrum_fft(*args(ptr=None)) == 1
     assert lib.sfhk_spectrum_fft(*args(work=None)) == 1
     assert lib.sfhk_spectrum_fft(*args(nb=(32 << 10) - 1)) == 2
+    acc = lambda n_t=100, b=10, work=fake, nb=32 << 10, ptr=fake: (
+        ptr, n_t, -5.0, 0.1, 4.0, b, work, nb, ptr, None)
+    assert lib.sfhk_acceleration(*acc(n_t=0)) == 1
+    assert lib.sfhk_acceleration(*acc(b=6)) == 1
+    assert lib.sfhk_acceleration(*acc(ptr=None)) == 1
+    assert lib.sfhk_acceleration(*acc(nb=100)) == 2
 
 
 def test_missing_library_fails_loudly(monkeypatch):

@@ -430,6 +430,25 @@ def test_fft_spectrum_matches_oracle(sf, orc, case):
     assert np.max(np.abs(dph)) < 1e-6
 
 
+@pytest.mark.parametrize("case", ["h2_dipole", "random", "longer"])
+def test_acceleration_matches_oracle(sf, orc, case):
+    """The dipole acceleration on the step grid (sfhk_acceleration) against
+    the oracle's (the derivative through numpy's FFT, pinned to a closed
+    form), at the default and a longer padding."""
+    import torch
+    p = workloads.h2_softcore()
+    N, t0, tau = sf.problem_steps(p)
+    if case == "h2_dipole":
+        v, _, _ = orc.dipole(p, 1001, 0, 300, NTHREADS)
+    else:
+        v = np.random.default_rng(12).normal(size=N + 1)
+    log2 = 17 if case == "longer" else None
+    a = sf.acceleration(torch.tensor(v, device="cuda"), t0, p["dt"], tau / 2, log2)
+    torch.cuda.synchronize()
+    ao = orc.acceleration_fft(v, t0, p["dt"], tau / 2, log2)
+    assert rel_l2(a.cpu().numpy(), ao) < 1e-12
+
+
 def test_whole_path_spectrum_h2(sf, orc):
     """Dipole and harmonic spectrum of the H2 workload (harmonics 0..40)."""
     p = workloads.h2_softcore()
