@@ -494,7 +494,7 @@ def averaging_study(sf, mol, ionization, sizes, reps, n_ref, cap=False):
             "seconds": time.perf_counter() - t}
 
 
-def averaging_variant(sf, sizes=(1 << 14, 1 << 16, 1 << 18, 1 << 20), reps=4):
+def averaging_variant(sf, sizes=(1 << 14, 1 << 16, 1 << 18, 1 << 20), reps=6):
     """The averaging study for H2 and N2, each with the first-order sampler
     and with the saddle-point sampler whose weight carries the axis-dependent
     ionisation element (the Eq. 6 weight), each as sampled and with the
