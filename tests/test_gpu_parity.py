@@ -89,8 +89,10 @@ def test_sampling_matches_oracle(sf, orc, case):
             assert abs(o["w"][i] / p["w_cut"] - 1) < 1e-12
         both = live_g & live_o
         # transcendental results of the device library and of libm may differ
-        # by a few ulps; the weight's exponent (kappa^3/3)/F amplifies them
-        assert rel_err(g["w"][sl][both], o["w"][both]) < 1e-12
+        # by a few ulps; the weight's exponent (kappa^3/3)/F and the power of
+        # the Coulomb factor amplify them: measured at most 1.2e-13 over these
+        # cases
+        assert rel_err(g["w"][sl][both], o["w"][both]) < 5e-13
         for c, f in enumerate(("px", "py", "pz")):
             assert rel_err(g[f][sl], o["p0"][:, c], 1e-15) < 1e-13, f
         for c, f in enumerate(("nx", "ny", "nz")):  # unit vector: absolute error
