@@ -248,6 +248,49 @@ template <> struct PotConst<float> {
   __device__ static float a2dZ(const Desc& d, int c) { return d.fa2dZ[c]; }
 };
 
+// Sources of the potential's constants: the problem descriptor, read at
+// each use (PotDesc), or values a kernel keeps in registers for a whole
+// loop (PotK: the FP64 constants, or their FP32 roundings).
+template <typename T>
+struct PotDesc {
+  const Desc& d;
+  __device__ T Zinf(int c) const { return PotConst<T>::Zinf(d, c); }
+  __device__ T dZ(int c) const { return PotConst<T>::dZ(d, c); }
+  __device__ T alpha(int c) const { return PotConst<T>::alpha(d, c); }
+  __device__ T eps2(int c) const { return PotConst<T>::eps2(d, c); }
+  __device__ T adZ(int c) const { return PotConst<T>::adZ(d, c); }
+  __device__ T a2dZ(int c) const { return PotConst<T>::a2dZ(d, c); }
+  __device__ bool screened() const { return d.screened != 0; }
+};
+template <typename T>
+struct PotK {
+  T v[6][2];  // Zinf, dZ, alpha, eps2, adZ, a2dZ of both centres
+  bool scr;
+  __device__ T Zinf(int c) const { return v[0][c]; }
+  __device__ T dZ(int c) const { return v[1][c]; }
+  __device__ T alpha(int c) const { return v[2][c]; }
+  __device__ T eps2(int c) const { return v[3][c]; }
+  __device__ T adZ(int c) const { return v[4][c]; }
+  __device__ T a2dZ(int c) const { return v[5][c]; }
+  __device__ bool screened() const { return scr; }
+};
+template <typename T>
+__device__ __forceinline__ PotK<T> pot_k(const Desc& d) {
+  const PotDesc<T> s{d};
+  PotK<T> k;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    k.v[0][c] = s.Zinf(c);
+    k.v[1][c] = s.dZ(c);
+    k.v[2][c] = s.alpha(c);
+    k.v[3][c] = s.eps2(c);
+    k.v[4][c] = s.adZ(c);
+    k.v[5][c] = s.a2dZ(c);
+  }
+  k.scr = s.screened();
+  return k;
+}
+
 // Two-centre potential of Eq. 7 with softened distance (per centre
 // V_i = -Z_i(rho)/rho, Z_i = Zinf + dZ u, u = e^{-alpha rho},
 // rho^2 = |q-R_i|^2 + eps2): value, gradient and the symmetric Hessian K
@@ -266,25 +309,28 @@ struct Geom {
   T dx[2], dy[2], dz[2], r2[2];
 };
 
-template <typename T>
-__device__ __forceinline__ void geometry(const Desc& d, const T hRn[3], const T q[3],
-                                         Geom<T>& G) {
+template <typename T, typename P>
+__device__ __forceinline__ void geometry_p(const P& k, const T hRn[3], const T q[3],
+                                           Geom<T>& G) {
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     G.dx[c] = c == 0 ? q[0] - hRn[0] : q[0] + hRn[0];
     G.dy[c] = c == 0 ? q[1] - hRn[1] : q[1] + hRn[1];
     G.dz[c] = c == 0 ? q[2] - hRn[2] : q[2] + hRn[2];
-    G.r2[c] = fma(G.dz[c], G.dz[c],
-                  fma(G.dy[c], G.dy[c], fma(G.dx[c], G.dx[c], PotConst<T>::eps2(d, c))));
+    G.r2[c] = fma(G.dz[c], G.dz[c], fma(G.dy[c], G.dy[c], fma(G.dx[c], G.dx[c], k.eps2(c))));
   }
+}
+template <typename T>
+__device__ __forceinline__ void geometry(const Desc& d, const T hRn[3], const T q[3],
+                                         Geom<T>& G) {
+  geometry_p(PotDesc<T>{d}, hRn, q, G);
 }
 
 // ek: the exponential's constants in VGPRs (FP64 only; null: built in
 // SGPRs at their use).
-template <typename T>
-__device__ __forceinline__ void potential(const Desc& d, const Geom<T>& G, T& V, T g[3],
-                                          T K[6], const ExpK* ek = nullptr) {
-  using PC = PotConst<T>;
+template <typename T, typename P>
+__device__ __forceinline__ void potential_p(const P& k, const Geom<T>& G, T& V, T g[3], T K[6],
+                                            const ExpK* ek = nullptr) {
   const T* dx = G.dx;
   const T* dy = G.dy;
   const T* dz = G.dz;
@@ -292,11 +338,11 @@ __device__ __forceinline__ void potential(const Desc& d, const Geom<T>& G, T& V,
   T s[2], u[2] = {T(0), T(0)};
 #pragma unroll
   for (int c = 0; c < 2; ++c) s[c] = rsqrt_t(r2[c]);
-  if (d.screened) {
+  if (k.screened()) {
     // both centres' screening factors at once (an electron far from one
     // centre is far from the other); the argument is capped where e^{-y}
     // is far below a rounding unit of Z_inf
-    const T ar0 = PC::alpha(d, 0) * (r2[0] * s[0]), ar1 = PC::alpha(d, 1) * (r2[1] * s[1]);
+    const T ar0 = k.alpha(0) * (r2[0] * s[0]), ar1 = k.alpha(1) * (r2[1] * s[1]);
     if (ar0 < T(kScreenFar) || ar1 < T(kScreenFar)) {
       const T y0 = fmin(ar0, T(kScreenCap)), y1 = fmin(ar1, T(kScreenCap));
       if constexpr (sizeof(T) == sizeof(double)) {
@@ -316,12 +362,12 @@ __device__ __forceinline__ void potential(const Desc& d, const Geom<T>& G, T& V,
   T diag = T(0);
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    const T Z = PC::Zinf(d, c) + PC::dZ(d, c) * u[c];
-    const T t = Z * s[c] + PC::adZ(d, c) * u[c];
+    const T Z = k.Zinf(c) + k.dZ(c) * u[c];
+    const T t = Z * s[c] + k.adZ(c) * u[c];
     const T s2 = s[c] * s[c];
     const T c1 = s2 * t;  // V_i'/rho
     // c2 = -s^3 (3 s t + alpha^2 dZ u) = -s^2 (3 c1 + alpha^2 dZ u s)
-    const T c2 = -s2 * fma(T(3), c1, PC::a2dZ(d, c) * u[c] * s[c]);
+    const T c2 = -s2 * fma(T(3), c1, k.a2dZ(c) * u[c] * s[c]);
     V -= Z * s[c];
     g[0] += c1 * dx[c];
     g[1] += c1 * dy[c];
@@ -340,6 +386,11 @@ __device__ __forceinline__ void potential(const Desc& d, const Geom<T>& G, T& V,
   K[2] += diag;
 }
 
+template <typename T>
+__device__ __forceinline__ void potential(const Desc& d, const Geom<T>& G, T& V, T g[3],
+                                          T K[6], const ExpK* ek = nullptr) {
+  potential_p(PotDesc<T>{d}, G, V, g, K, ek);
+}
 template <typename T>
 __device__ __forceinline__ void potential(const Desc& d, const T hRn[3], const T q[3], T& V,
                                           T g[3], T K[6], const ExpK* ek = nullptr) {

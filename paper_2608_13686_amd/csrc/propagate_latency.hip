@@ -297,22 +297,23 @@ __device__ __forceinline__ bool find_unit(const EnsPtrs& e, int n_prob, uint32_t
 // ------------------------------------------------------------ pipelined
 // The same latency form on two wavefronts per unit of 8 trajectories, so that
 // the two halves of a step run on two SIMDs at once: wavefront 0 (the orbit
-// wavefront, lane g for trajectory g) integrates (q, p, S) and evaluates the
-// four stage Hessians; wavefront 1 (the monodromy wavefront, 8 lanes per
-// trajectory as above) takes the prefactor, amplitude and deposit at step k
-// and advances its columns with the Hessians of step k.  The orbit wavefront
-// runs one step ahead: in iteration i it writes step i's state and Hessians
-// into ring slot i mod 2 of LDS while the monodromy wavefront reads step
-// i - 1's from the other slot; one workgroup barrier per iteration hands the
-// slots over.  The monodromy wavefront also spreads the recombination
-// amplitude's shells over the 8 lanes of the group and keeps each step's
-// amplitudes in LDS, summing them across trajectories once every 64 steps.
-// The orbit, the columns and the prefactor take the one-wavefront form's
-// operations on the same operands in the same order; the amplitude's and
-// the dipole's sums are ordered differently (rounding-level differences).
-// The orbit of a trajectory stopped by the prefactor cap is integrated on
-// but not used; records (which hold the stopping step's state) use the
-// one-wavefront form.
+// wavefront, lanes 2g and 2g + 1 for trajectory g) integrates (q, p, S) and
+// evaluates the four stage Hessians, two stages per lane; wavefront 1 (the
+// monodromy wavefront, 8 lanes per trajectory as above) takes the
+// prefactor, amplitude and deposit at step k and advances its columns with
+// the Hessians of step k.  The orbit wavefront runs one step ahead: in
+// iteration i it writes step i's state and Hessians into ring slot i mod 2
+// of LDS while the monodromy wavefront reads step i - 1's from the other
+// slot; one workgroup barrier per iteration hands the slots over.  The
+// monodromy wavefront spreads det R over lanes 0-2 (one cofactor term each),
+// the recombination amplitude's shells over the 8 lanes of the group, and
+// keeps each step's amplitudes in LDS, summing them across trajectories once
+// every 64 steps.  The orbit and the columns take the one-wavefront form's
+// operations on the same operands in the same order; det R's, the
+// amplitude's and the dipole's sums are ordered differently
+// (rounding-level differences).  The orbit of a trajectory stopped by the
+// prefactor cap is integrated on but not used; records (which hold the
+// stopping step's state) use the one-wavefront form.
 constexpr int kPipeThreads = 2 * kWave;
 
 // 32-bit DPP move of both halves of a double (control code Ctl)
@@ -336,21 +337,34 @@ __device__ __forceinline__ double group_sum(double x) {
   return x + dpp64<0x141>(x);  // row_half_mirror
 }
 
+// Lane 0's value of x on every lane of its group of 8: the quad broadcast,
+// then the half-row mirror written into the upper quad only (bank mask).
+__device__ __forceinline__ int group_bcast0(int x) {
+  const int y = __builtin_amdgcn_update_dpp(0, x, 0x00, 0xf, 0xf, false);  // quad_perm [0,0,0,0]
+  return __builtin_amdgcn_update_dpp(y, y, 0x141, 0xf, 0xA, false);        // row_half_mirror
+}
+
 // The recombination amplitude of amplitude_re with the shells spread over
 // the 8 lanes of the trajectory's group (lane c takes shells c, c + 8, ...),
 // the phase factor evaluated on every lane beside them, and the shells'
 // sums gathered by group_sum: the same terms as amplitude_re, summed in a
-// different order.  Every lane of the group returns the value.
-__device__ __forceinline__ double amplitude_re_group(const Desc& d, const double n[3],
-                                                     const double p[3], const Geom<double>& G,
+// different order.  The gate takes the nearest centre's squared distance
+// dd_min and the binary exponent of 1 + |C|^2 (ex, lane 0's, on every lane
+// of the group); the geometry at q is built only past the gate.  The value
+// is lane 0's (the other lanes' C is not the trajectory's).
+__device__ __forceinline__ double amplitude_re_group(const Desc& d, const PotK<double>& pk,
+                                                     double g_inv4k_min, const double hRn[3],
+                                                     const double n[3], const double q[3],
+                                                     const double p[3], double dd_min, int ex,
                                                      double Cre, double Cim, double S,
                                                      double tk, double t0, double p0q0,
                                                      double w, int c) {
+  const double lnC = 0.3466 * (double)ex;
+  if (dd_min * g_inv4k_min + kRecombFar > lnC) return 0.0;  // group-uniform
+  Geom<double> G;
+  geometry_p(pk, hRn, q, G);
   const double pp = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
-  const double dd[2] = {G.r2[0] - d.eps2[0], G.r2[1] - d.eps2[1]};
-  const double cc = 1.0 + Cre * Cre + Cim * Cim;
-  const double lnC = 0.3466 * (double)(((int)(__double_as_longlong(cc) >> 52) & 0x7ff) - 1022);
-  if (fmin(dd[0], dd[1]) * d.g_inv4k_min + kRecombFar > lnC) return 0.0;  // group-uniform
+  const double dd[2] = {G.r2[0] - pk.eps2(0), G.r2[1] - pk.eps2(1)};
   const double np_ = n[0] * p[0] + n[1] * p[1] + n[2] * p[2];
   const double bzr = p[2] * d.inv_gamma;
   const double nbr = np_ * d.inv_gamma;
@@ -392,7 +406,7 @@ __device__ __forceinline__ double amplitude_re_group(const Desc& d, const double
 
 struct PipeRing {
   double K[2][4][6][kPerWave];  // slot, RK4 stage, Hessian entry, trajectory
-  double st[2][7][kPerWave];    // slot, (q, p, S) at the step, trajectory
+  double st[2][8][kPerWave];    // slot, (q, p, S, dd_min) at the step, trajectory
   double dep[kWave][kPerWave];  // Re a of the last 64 steps (step mod 64, trajectory)
 };
 
@@ -405,7 +419,7 @@ __device__ __forceinline__ void run_pipe_unit(const Desc* __restrict__ descs,
   const int N = d.N;
   const bool orbit_wave = threadIdx.x < kWave;
   const int lane = threadIdx.x & (kWave - 1);
-  const int g = orbit_wave ? lane : lane / kGroup;  // trajectory of the unit
+  const int g = orbit_wave ? lane >> 1 : lane / kGroup;  // trajectory of the unit
   const int c = lane & (kGroup - 1);                 // monodromy column
   const uint32_t pos = unit_pos + (uint32_t)g;
   const bool valid = g < kPerWave && pos < e.live_count[prob];
@@ -421,29 +435,81 @@ __device__ __forceinline__ void run_pipe_unit(const Desc* __restrict__ descs,
   double S = 0.0;
 
   if (orbit_wave) {
+    // Lanes 2g and 2g + 1 both hold trajectory g's (q, p, S).  RK4's stages
+    // 1 and 2 are evaluated at q and q + h/2 p, so they depend on (q, p)
+    // only; stage 3's point needs stage 1's force only, stage 4's stage 2's.
+    // Lane j of the pair evaluates stages 1 + j and 3 + j (j = 0: q, then
+    // q + h/2 (p + h/2 F1); j = 1: q + h/2 p, then q + h (p + h/2 F2)), writes
+    // their Hessians, and the pair exchanges the four gradients and
+    // potentials; both lanes then combine the stages in the classical order,
+    // with the same operations as a one-lane step.
+    const int j = lane & 1;
     const double* __restrict__ fe = field + d.field_off;
     const ExpK ekv = make_expk();
+    // the potential's constants in VGPRs for the whole loop (opaque, so the
+    // compiler neither reloads them from the descriptor nor keeps them in
+    // scarce SGPRs)
+    PotK<double> pk = pot_k<double>(d);
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int ce = 0; ce < 2; ++ce) asm volatile("" : "+v"(pk.v[r][ce]));
+    const double cA = j ? hh : 0.0, cB = j ? h : hh;
     for (int i = kmin; i <= N + 1; ++i) {
       if (valid && i <= N) {
         const int sl = i & 1;
+        double yq[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          ring.st[sl][a][g] = q[a];
-          ring.st[sl][3 + a][g] = p[a];
+        for (int a = 0; a < 3; ++a) yq[a] = q[a] + cA * p[a];  // lane 0: q exactly
+        Geom<double> G;
+        geometry_p(pk, hRn, yq, G);
+        if (j == 0) {
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            ring.st[sl][a][g] = q[a];
+            ring.st[sl][3 + a][g] = p[a];
+          }
+          ring.st[sl][6][g] = S;
+          // the recombination gate's nearest-centre squared distance at q
+          ring.st[sl][7][g] = fmin(G.r2[0] - pk.eps2(0), G.r2[1] - pk.eps2(1));
         }
-        ring.st[sl][6][g] = S;
         if (i >= k0 && i < N) {
           const double Ek = fe[2 * i], Eh = fe[2 * i + 1], E1 = fe[2 * i + 2];
-          double K[6], V, gr[3];
-          double sq[3], sp3[3], sS, yq[3], yp[3];
-          Geom<double> Gk;
-          geometry(d, hRn, q, Gk);
-          potential(d, Gk, V, gr, K, &ekv);
+          double yp[3], VA, VB, gA[3], gB[3], K[6];
+          potential_p(pk, G, VA, gA, K, &ekv);
 #pragma unroll
-          for (int j = 0; j < 6; ++j) ring.K[sl][0][j][g] = K[j];
+          for (int jj = 0; jj < 6; ++jj) ring.K[sl][j][jj][g] = K[jj];
           {
-            const double kp[3] = {-gr[0], -gr[1], -gr[2] - Ek};
-            sS = 0.5 * (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]) - V - q[2] * Ek;
+            const double EA = j ? Eh : Ek;
+            const double kp[3] = {-gA[0], -gA[1], -gA[2] - EA};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              yp[a] = p[a] + hh * kp[a];  // p at stage 2 (lane 0), stage 3 (lane 1)
+              yq[a] = q[a] + cB * yp[a];  // stage 3 (lane 0), stage 4 (lane 1)
+            }
+          }
+          geometry_p(pk, hRn, yq, G);
+          potential_p(pk, G, VB, gB, K, &ekv);
+#pragma unroll
+          for (int jj = 0; jj < 6; ++jj) ring.K[sl][2 + j][jj][g] = K[jj];
+          // stage s's gradient and potential on both lanes: from lane
+          // (s - 1) & 1 of the pair (quad permutations [0,0,2,2], [1,1,3,3])
+          double gr[4][3], V[4];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            gr[0][a] = dpp64<0xA0>(gA[a]);
+            gr[1][a] = dpp64<0xF5>(gA[a]);
+            gr[2][a] = dpp64<0xA0>(gB[a]);
+            gr[3][a] = dpp64<0xF5>(gB[a]);
+          }
+          V[0] = dpp64<0xA0>(VA);
+          V[1] = dpp64<0xF5>(VA);
+          V[2] = dpp64<0xA0>(VB);
+          V[3] = dpp64<0xF5>(VB);
+          double sq[3], sp3[3], sS;
+          {
+            const double kp[3] = {-gr[0][0], -gr[0][1], -gr[0][2] - Ek};
+            sS = 0.5 * (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]) - V[0] - q[2] * Ek;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
               sq[a] = p[a];
@@ -452,12 +518,9 @@ __device__ __forceinline__ void run_pipe_unit(const Desc* __restrict__ descs,
               yp[a] = p[a] + hh * kp[a];
             }
           }
-          potential(d, hRn, yq, V, gr, K, &ekv);
-#pragma unroll
-          for (int j = 0; j < 6; ++j) ring.K[sl][1][j][g] = K[j];
           {
-            const double kp[3] = {-gr[0], -gr[1], -gr[2] - Eh};
-            sS += 2.0 * (0.5 * (yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]) - V - yq[2] * Eh);
+            const double kp[3] = {-gr[1][0], -gr[1][1], -gr[1][2] - Eh};
+            sS += 2.0 * (0.5 * (yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]) - V[1] - yq[2] * Eh);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
               const double kq = yp[a];
@@ -467,12 +530,9 @@ __device__ __forceinline__ void run_pipe_unit(const Desc* __restrict__ descs,
               yp[a] = p[a] + hh * kp[a];
             }
           }
-          potential(d, hRn, yq, V, gr, K, &ekv);
-#pragma unroll
-          for (int j = 0; j < 6; ++j) ring.K[sl][2][j][g] = K[j];
           {
-            const double kp[3] = {-gr[0], -gr[1], -gr[2] - Eh};
-            sS += 2.0 * (0.5 * (yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]) - V - yq[2] * Eh);
+            const double kp[3] = {-gr[2][0], -gr[2][1], -gr[2][2] - Eh};
+            sS += 2.0 * (0.5 * (yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]) - V[2] - yq[2] * Eh);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
               const double kq = yp[a];
@@ -482,12 +542,9 @@ __device__ __forceinline__ void run_pipe_unit(const Desc* __restrict__ descs,
               yp[a] = p[a] + h * kp[a];
             }
           }
-          potential(d, hRn, yq, V, gr, K, &ekv);
-#pragma unroll
-          for (int j = 0; j < 6; ++j) ring.K[sl][3][j][g] = K[j];
           {
-            const double kp[3] = {-gr[0], -gr[1], -gr[2] - E1};
-            sS += 0.5 * (yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]) - V - yq[2] * E1;
+            const double kp[3] = {-gr[3][0], -gr[3][1], -gr[3][2] - E1};
+            sS += 0.5 * (yp[0] * yp[0] + yp[1] * yp[1] + yp[2] * yp[2]) - V[3] - yq[2] * E1;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
               sq[a] += yp[a];
@@ -519,6 +576,17 @@ __device__ __forceinline__ void run_pipe_unit(const Desc* __restrict__ descs,
   double* __restrict__ acc = accum + d.acc_off;
   const double gamma = d.gamma, inv_gamma = d.inv_gamma;
   int kend = N + 1;
+  // per-step constants in registers for the whole loop (opaque: neither
+  // reloaded from the descriptor nor rematerialised)
+  PotK<double> pk = pot_k<double>(d);
+#pragma unroll
+  for (int r = 0; r < 6; ++r)
+#pragma unroll
+    for (int ce = 0; ce < 2; ++ce) asm volatile("" : "+v"(pk.v[r][ce]));
+  double c_max2 = d.c_max2, g_inv4k_min = d.g_inv4k_min;
+  asm volatile("" : "+v"(c_max2), "+v"(g_inv4k_min));
+  int capped = __builtin_amdgcn_readfirstlane(d.c_max2 > 0.0 ? 1 : 0);
+  asm volatile("" : "+s"(capped));
   __syncthreads();  // iteration kmin: the orbit wavefront writes step kmin
   for (int k = kmin; k <= N; ++k) {
     const int sl = k & 1;
@@ -529,6 +597,7 @@ __device__ __forceinline__ void run_pipe_unit(const Desc* __restrict__ descs,
       p[a] = ring.st[sl][3 + a][g];
     }
     S = ring.st[sl][6][g];
+    const double dd_min = ring.st[sl][7][g];
     double x3[3], v3[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -541,32 +610,37 @@ __device__ __forceinline__ void run_pipe_unit(const Desc* __restrict__ descs,
       rr[r] = x[r] + v3[r];
       ri[r] = fma(inv_gamma, v[r], -gamma * x3[r]);
     }
-    double Rr[3][3], Ri[3][3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      Rr[r][0] = rr[r];
-      Ri[r][0] = ri[r];
-      Rr[r][1] = from_lane_plus<1>(rr[r]);
-      Ri[r][1] = from_lane_plus<1>(ri[r]);
-      Rr[r][2] = from_lane_plus<2>(rr[r]);
-      Ri[r][2] = from_lane_plus<2>(ri[r]);
-    }
+    // det 2R by the cyclic cofactor expansion along row 0: lane c < 3 takes
+    // the term of column c, its minor from columns c + 1 and c + 2 (mod 3)
+    // of rows 1 and 2 (quad permutations [1,2,0,3] and [2,0,1,3]); lane 3's
+    // term is zero, and two quad exchanges sum the terms on lane 0
+    const double a1r = dpp64<0xC9>(rr[1]), a1i = dpp64<0xC9>(ri[1]);  // R[1][c+1]
+    const double a2r = dpp64<0xC9>(rr[2]), a2i = dpp64<0xC9>(ri[2]);  // R[2][c+1]
+    const double b1r = dpp64<0xD2>(rr[1]), b1i = dpp64<0xD2>(ri[1]);  // R[1][c+2]
+    const double b2r = dpp64<0xD2>(rr[2]), b2i = dpp64<0xD2>(ri[2]);  // R[2][c+2]
+    const double mr = fma(a1r, b2r, fma(-a1i, b2i, fma(-b1r, a2r, b1i * a2i)));
+    const double mi = fma(a1r, b2i, fma(a1i, b2r, fma(-b1r, a2i, -(b1i * a2r))));
+    double tr = c < 3 ? fma(rr[0], mr, -(ri[0] * mi)) : 0.0;
+    double ti = c < 3 ? fma(rr[0], mi, ri[0] * mr) : 0.0;
+    tr += dpp64<0xB1>(tr);
+    ti += dpp64<0xB1>(ti);
+    tr += dpp64<0x4E>(tr);
+    ti += dpp64<0x4E>(ti);
     double re_a = 0.0;
     if (live && c == 0) {
-      prefactor_step(Rr, Ri, Cre, Cim, flips);
-      if (d.c_max2 > 0.0 && Cre * Cre + Cim * Cim > d.c_max2) kend = k;
+      sqrt_continued(0.125 * tr, 0.125 * ti, Cre, Cim, flips);
+      if (capped && Cre * Cre + Cim * Cim > c_max2) kend = k;
     }
-    if (d.c_max2 > 0.0) {  // the cap decision of lane 0 holds for its whole group
+    if (capped) {  // the cap decision of lane 0 holds for its whole group
       kend = __shfl(kend, lane & ~(kGroup - 1), kWave);
       live = k >= k0 && k < kend;
     }
     if (live && k >= kdep) {  // group-uniform
-      // C of lane 0 on every lane of the group (the others add zeros)
-      const double cre = group_sum(c == 0 ? Cre : 0.0), cim = group_sum(c == 0 ? Cim : 0.0);
-      Geom<double> Gk;
-      geometry(d, hRn, q, Gk);
-      const double a = amplitude_re_group(d, n, p, Gk, cre, cim, S, d.t_first + (double)k * h,
-                                          t0, p0q0, w, c);
+      // the binary exponent of 1 + |C|^2 of lane 0 for the gate
+      const double cc = 1.0 + Cre * Cre + Cim * Cim;
+      const int ex = group_bcast0(((int)(__double_as_longlong(cc) >> 52) & 0x7ff) - 1022);
+      const double a = amplitude_re_group(d, pk, g_inv4k_min, hRn, n, q, p, dd_min, ex, Cre, Cim,
+                                          S, d.t_first + (double)k * h, t0, p0q0, w, c);
       re_a = c == 0 ? a : 0.0;
     }
     // deposit: each trajectory's Re a_k goes to LDS (no cross-lane sum per
