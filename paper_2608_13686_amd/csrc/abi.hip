@@ -455,9 +455,13 @@ sfhk_status propagate_enqueue(int n_prob, const sfhk_ensemble* ens, int precisio
       e2.live_start = po.live_start;
       e2.live_count = po.live_count;
       e2.pack_start = po.pack_start;
-      // the handed-over trajectories are few: latency form
+      // the handed-over trajectories are few: latency form (units of two
+      // monodromy wavefronts when the launch is above the latency threshold:
+      // hundreds of units share the SIMDs)
+      LaunchCfg lc;
+      lc.pipe_mono = max_packs > kLatencyMaxPacks ? 2 : 1;
       e = launch_propagate_latency(ws.descs, n_prob, ws.field, e2, ws.redo, (uint32_t)max_packs,
-                                   accum, rec, s, LaunchCfg{});
+                                   accum, rec, s, lc);
     }
   }
   if (e != hipSuccess) return hip_fail(e, "propagate");
@@ -857,6 +861,9 @@ sfhk_status plan_enqueue(sfhk_plan* P, hipStream_t s, bool timed) {
       cfg2.counter = P->counter + 1;
       const bool lat = P->tune.lanes_per_traj == 8;
       if (lat && cfg.persistent) cfg2.grid = P->grid_latency;
+      // the re-run of a launch above the latency threshold puts hundreds of
+      // units on the SIMDs at once: units of two monodromy wavefronts
+      cfg2.pipe_mono = mp > kLatencyMaxPacks ? 2 : 1;
       if (e == hipSuccess && cfg.persistent)
         e = launch_pack_queue(ws.descs, n_prob, e2, mp, P->L.n_len, P->qkeys, P->qhist,
                               P->qcursor, P->queue2, s);

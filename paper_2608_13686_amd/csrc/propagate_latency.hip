@@ -280,7 +280,9 @@ __device__ __forceinline__ void run_unit(const Desc* __restrict__ descs,
   }
 }
 
-// Unit u of the launch: pack u / 8, positions 8 (u % 8) .. + 7 of it.
+// Unit sub of a pack of 64 trajectories, units of U trajectories: positions
+// U sub .. U sub + U - 1 of the pack.
+template <int U = kPerWave>
 __device__ __forceinline__ bool find_unit(const EnsPtrs& e, int n_prob, uint32_t pack,
                                           uint32_t sub, int& prob, uint32_t& unit_pos) {
   if (pack >= e.pack_start[n_prob]) return false;
@@ -290,7 +292,7 @@ __device__ __forceinline__ bool find_unit(const EnsPtrs& e, int n_prob, uint32_t
     if (e.pack_start[mid] <= pack) lo = mid; else hi = mid;
   }
   prob = lo;
-  unit_pos = (pack - e.pack_start[lo]) * kWave + sub * kPerWave;
+  unit_pos = (pack - e.pack_start[lo]) * kWave + sub * U;
   return unit_pos < e.live_count[lo];
 }
 
@@ -314,7 +316,13 @@ __device__ __forceinline__ bool find_unit(const EnsPtrs& e, int n_prob, uint32_t
 // (rounding-level differences).  The orbit of a trajectory stopped by the
 // prefactor cap is integrated on but not used; records (which hold the
 // stopping step's state) use the one-wavefront form.
-constexpr int kPipeThreads = 2 * kWave;
+// A unit of M monodromy wavefronts holds 8 M trajectories; its orbit
+// wavefront uses 16 M of its lanes.  M = 2 halves the orbit wavefronts of a
+// crowded launch (many units per SIMD: the issue slots they take are the
+// step time); one unit alone steps faster with M = 1.
+template <int M> constexpr int pipe_traj() { return M * kPerWave; }
+template <int M> constexpr int pipe_units_per_pack() { return kWave / pipe_traj<M>(); }
+template <int M> constexpr int pipe_threads() { return (1 + M) * kWave; }
 
 // 32-bit DPP move of both halves of a double (control code Ctl)
 template <int Ctl>
@@ -404,25 +412,30 @@ __device__ __forceinline__ double amplitude_re_group(const Desc& d, const PotK<d
   return -w * (er_ * rr - ei_ * ri);
 }
 
+template <int M>
 struct PipeRing {
-  double K[2][4][6][kPerWave];  // slot, RK4 stage, Hessian entry, trajectory
-  double st[2][8][kPerWave];    // slot, (q, p, S, dd_min) at the step, trajectory
-  double dep[kWave][kPerWave];  // Re a of the last 64 steps (step mod 64, trajectory)
+  static constexpr int T = pipe_traj<M>();
+  double K[2][4][6][T];  // slot, RK4 stage, Hessian entry, trajectory
+  double st[2][8][T];    // slot, (q, p, S, dd_min) at the step, trajectory
+  double dep[kWave][T];  // Re a of the last 64 steps (step mod 64, trajectory)
 };
 
+template <int M>
 __device__ __forceinline__ void run_pipe_unit(const Desc* __restrict__ descs,
                                               const double* __restrict__ field, const EnsPtrs& e,
                                               const int32_t* __restrict__ dep_from,
                                               double* __restrict__ accum, int prob,
-                                              uint32_t unit_pos, PipeRing& ring) {
+                                              uint32_t unit_pos, PipeRing<M>& ring) {
   const Desc& d = descs[prob];
   const int N = d.N;
-  const bool orbit_wave = threadIdx.x < kWave;
+  const int wave = threadIdx.x / kWave;  // 0: orbit, 1 ..: monodromy
+  const bool orbit_wave = wave == 0;
   const int lane = threadIdx.x & (kWave - 1);
-  const int g = orbit_wave ? lane >> 1 : lane / kGroup;  // trajectory of the unit
-  const int c = lane & (kGroup - 1);                 // monodromy column
+  const int mw0 = orbit_wave ? 0 : (wave - 1) * kPerWave;  // first trajectory of the wavefront
+  const int g = orbit_wave ? lane >> 1 : mw0 + lane / kGroup;  // trajectory of the unit
+  const int c = lane & (kGroup - 1);                           // monodromy column
   const uint32_t pos = unit_pos + (uint32_t)g;
-  const bool valid = g < kPerWave && pos < e.live_count[prob];
+  const bool valid = g < pipe_traj<M>() && pos < e.live_count[prob];
   const uint32_t slot = valid ? e.order[e.live_start[prob] + pos] : 0u;
   const int k0 = valid ? e.k0[slot] : N + 1;
   // the unit's first trajectory is born first (sorted by birth step)
@@ -655,7 +668,7 @@ __device__ __forceinline__ void run_pipe_unit(const Desc* __restrict__ descs,
       if (lane <= (k & (kWave - 1)) && kb + lane >= kmin) {
         double tot = 0.0;
 #pragma unroll
-        for (int t = 0; t < kPerWave; ++t) tot += ring.dep[lane][t];
+        for (int t = 0; t < kPerWave; ++t) tot += ring.dep[lane][mw0 + t];
         if (tot != 0.0) unsafeAtomicAdd(&acc[kb + lane], tot);
       }
     }
@@ -708,27 +721,33 @@ __device__ __forceinline__ void run_pipe_unit(const Desc* __restrict__ descs,
   }
 }
 
-__global__ void __launch_bounds__(kPipeThreads)
+template <int M>
+__global__ void __launch_bounds__(pipe_threads<M>())
 propagate_pipe_kernel(const Desc* __restrict__ descs, int n_prob,
                       const double* __restrict__ field, EnsPtrs e,
                       const int32_t* __restrict__ dep_from, double* __restrict__ accum) {
-  __shared__ PipeRing ring;
+  __shared__ PipeRing<M> ring;
+  constexpr int kU = pipe_units_per_pack<M>();
   int prob;
   uint32_t unit_pos;
-  if (!find_unit(e, n_prob, blockIdx.x / kPerWave, blockIdx.x % kPerWave, prob, unit_pos)) return;
-  run_pipe_unit(descs, field, e, dep_from, accum, prob, unit_pos, ring);
+  if (!find_unit<pipe_traj<M>()>(e, n_prob, blockIdx.x / kU, blockIdx.x % kU, prob, unit_pos))
+    return;
+  run_pipe_unit<M>(descs, field, e, dep_from, accum, prob, unit_pos, ring);
 }
 
-// Persistent form: a fixed grid of workgroups pulls units (pack queue[u / 8],
-// positions 8 (u % 8) ..) through an atomic counter until all are taken.
-__global__ void __launch_bounds__(kPipeThreads)
+// Persistent form: a fixed grid of workgroups pulls units (pack
+// queue[u / units per pack], unit u % units per pack of it) through an
+// atomic counter until all are taken.
+template <int M>
+__global__ void __launch_bounds__(pipe_threads<M>())
 propagate_pipe_persistent(const Desc* __restrict__ descs, int n_prob,
                           const double* __restrict__ field, EnsPtrs e,
                           const int32_t* __restrict__ dep_from, double* __restrict__ accum,
                           const uint32_t* __restrict__ queue, uint32_t* __restrict__ counter) {
-  __shared__ PipeRing ring;
+  __shared__ PipeRing<M> ring;
   __shared__ uint32_t next;
-  const uint32_t total = e.pack_start[n_prob] * (uint32_t)kPerWave;
+  constexpr int kU = pipe_units_per_pack<M>();
+  const uint32_t total = e.pack_start[n_prob] * (uint32_t)kU;
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
     __syncthreads();
@@ -737,9 +756,26 @@ propagate_pipe_persistent(const Desc* __restrict__ descs, int n_prob,
     if (u >= total) break;
     int prob;
     uint32_t unit_pos;
-    if (!find_unit(e, n_prob, queue[u / kPerWave], u % kPerWave, prob, unit_pos)) continue;
-    run_pipe_unit(descs, field, e, dep_from, accum, prob, unit_pos, ring);
+    if (!find_unit<pipe_traj<M>()>(e, n_prob, queue[u / kU], u % kU, prob, unit_pos)) continue;
+    run_pipe_unit<M>(descs, field, e, dep_from, accum, prob, unit_pos, ring);
   }
+}
+
+template <int M>
+hipError_t launch_pipe(const Desc* descs, int n_prob, const double* field, EnsPtrs e,
+                       const int32_t* dep_from, uint32_t max_packs, double* accum, hipStream_t s,
+                       const LaunchCfg& cfg) {
+  if (cfg.persistent) {
+    // cfg.grid counts wavefronts: 1 + M per workgroup
+    const uint32_t grid = cfg.grid / (1 + M) > 0 ? cfg.grid / (1 + M) : 1;
+    hipLaunchKernelGGL(propagate_pipe_persistent<M>, dim3(grid), dim3(pipe_threads<M>()), 0, s,
+                       descs, n_prob, field, e, dep_from, accum, cfg.queue, cfg.counter);
+  } else {
+    const uint32_t units = (uint32_t)((uint64_t)max_packs * pipe_units_per_pack<M>());
+    hipLaunchKernelGGL(propagate_pipe_kernel<M>, dim3(units), dim3(pipe_threads<M>()), 0, s,
+                       descs, n_prob, field, e, dep_from, accum);
+  }
+  return hipGetLastError();
 }
 
 template <bool Track>
@@ -761,19 +797,15 @@ hipError_t launch_propagate_latency(const Desc* descs, int n_prob, const double*
                                     double* accum, const Records& rec, hipStream_t s,
                                     const LaunchCfg& cfg) {
   if (max_packs == 0) return hipSuccess;
-  const uint32_t units = (uint32_t)((uint64_t)max_packs * kPerWave);
   if (rec.any()) {  // records: the one-wavefront form
+    const uint32_t units = (uint32_t)((uint64_t)max_packs * kPerWave);
     hipLaunchKernelGGL(propagate_latency_kernel<true>, dim3(units), dim3(kWave), 0, s, descs,
                        n_prob, field, e, dep_from, accum, rec);
-  } else if (cfg.persistent) {
-    const uint32_t grid = cfg.grid / 2 > 0 ? cfg.grid / 2 : 1;  // two wavefronts per workgroup
-    hipLaunchKernelGGL(propagate_pipe_persistent, dim3(grid), dim3(kPipeThreads), 0, s, descs,
-                       n_prob, field, e, dep_from, accum, cfg.queue, cfg.counter);
-  } else {
-    hipLaunchKernelGGL(propagate_pipe_kernel, dim3(units), dim3(kPipeThreads), 0, s, descs,
-                       n_prob, field, e, dep_from, accum);
+    return hipGetLastError();
   }
-  return hipGetLastError();
+  return cfg.pipe_mono == 2
+             ? launch_pipe<2>(descs, n_prob, field, e, dep_from, max_packs, accum, s, cfg)
+             : launch_pipe<1>(descs, n_prob, field, e, dep_from, max_packs, accum, s, cfg);
 }
 
 }  // namespace sfhk

@@ -175,6 +175,7 @@ struct LaunchCfg {
   uint32_t grid = 0;
   const uint32_t* queue = nullptr;
   uint32_t* counter = nullptr;
+  int pipe_mono = 1;  // latency form: monodromy wavefronts per unit (1 or 2)
 };
 
 // Optional per-slot records of a propagation (SFHK_FS_* layout, field-major,
