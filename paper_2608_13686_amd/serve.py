@@ -417,6 +417,38 @@ class Server:
         steps = int(self.window_ms * 1e3 / step)
         return max(1, min(max(self.window, steps), min(rest)))
 
+    def entries_for(self, picked, win):
+        """(request, k_from, k_to) of the next launch, in launch order.  Every
+        request advances `win` steps, except that, in time-targeted windows, a
+        request bound by its wavefronts' step latency (alone it would take
+        n x traj_step_us < step_us per step) advances as many steps as fit
+        into the launch's expected duration at two wavefronts per SIMD, while
+        the work so added stays under a quarter of the launch's.  Otherwise a
+        request of few trajectories and a long pulse would advance at the pace
+        of the launch's throughput-bound ones.  Requests taking more steps
+        come first, so that their longer-running packs start first."""
+        ents = [(r, r.k_next, min(r.k_next + win, r.n_steps + 1)) for r in picked]
+        if self.window_ms is None or len(ents) < 2:
+            return ents
+        groups = max(self.n_groups, 1)
+        t_step = max(self.step_us, sum(r.n_traj for r in picked) / groups * self.traj_step_us)
+        dur = win * t_step
+        w_lat = int(dur / (2.0 * self.step_us))
+        if w_lat <= win:
+            return ents
+        budget = 0.25 * dur
+        out = []
+        for r, a, b in ents:  # in priority order: the first picked gain first
+            per_step = r.n_traj / groups * self.traj_step_us
+            extra = min(r.n_steps + 1, a + w_lat) - b
+            if extra > 0 and r.n_traj * self.traj_step_us < self.step_us \
+                    and per_step * extra <= budget:
+                budget -= per_step * extra
+                b += extra
+            out.append((r, a, b))
+        out.sort(key=lambda e: e[1] - e[2])  # most steps first (stable)
+        return out
+
     def device_busy(self):
         """True while some pack group has `in_flight` windows outstanding."""
         for evs in self._events:
@@ -435,8 +467,7 @@ class Server:
         if not block and self.device_busy():
             return 0
         picked = self.pick()
-        win = self.window_for(picked)
-        entries = [(r, r.k_next, min(r.k_next + win, r.n_steps + 1)) for r in picked]
+        entries = self.entries_for(picked, self.window_for(picked))
         if entries:
             for g in range(self.n_groups):
                 evs = self._events[g]

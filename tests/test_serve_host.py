@@ -388,6 +388,32 @@ def test_time_targeted_windows():
         assert ent[0][2] - ent[0][1] >= 50 or any(b == ends[t] for t, _, b in ent)
 
 
+def test_latency_bound_request_takes_more_steps():
+    """Beside a throughput-bound request, a request of few trajectories
+    (alone bound by its step latency) advances as many steps as fit into the
+    launch's expected duration at two wavefronts per SIMD, and comes first in
+    the launch; its windows still cover its pulse once."""
+    x = FakeExec()
+    x.n_groups = 1
+    S = Server(x, pool_bytes=1 << 30, max_requests=8, window=50, device_waves=64,
+               window_ms=1.0, step_us=2.0, traj_step_us=1e-3)
+    S.submit("big", _prob(9000), 64 * 200, 0)  # 12,800 trajectories: 12.8 us per step alone
+    S.submit("small", _prob(9000), 64, 1)      # 64: bound by the 2 us step latency
+    S.admit()
+    S.step()
+    # one launch step: 12,864 x 1e-3 = 12.864 us -> 77 steps (~1 ms); at
+    # 2 x 2 us per step the small request fits 990.5 / 4 = 247 steps
+    assert x.launches[0][1] == [("small", 0, 247), ("big", 0, 77)]
+    S.drain()
+    for r in S.completed:
+        w = r.result["windows"]
+        assert w[0][0] == 0 and w[-1][1] == r.n_steps + 1
+        assert all(w[i][1] == w[i + 1][0] for i in range(len(w) - 1))
+    small = next(r for r in S.completed if r.tag == "small")
+    big = next(r for r in S.completed if r.tag == "big")
+    assert len(small.result["windows"]) < len(big.result["windows"])
+
+
 def test_server_rejects_bad_config():
     with pytest.raises(ValueError):
         Server(FakeExec(), 1 << 20, policy="lifo", window_ms=None)
