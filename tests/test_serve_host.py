@@ -414,6 +414,36 @@ def test_latency_bound_request_takes_more_steps():
     assert len(small.result["windows"]) < len(big.result["windows"])
 
 
+def test_srpt_bounds_lateness_against_fifo():
+    """A request more than one window behind its completion on a virtual FIFO
+    server (one request at a time in arrival order, each at its estimated
+    time alone) runs alone; until then shorter requests overtake it."""
+    now = [0.0]
+    x = FakeExec()
+    S = Server(x, pool_bytes=1 << 30, max_requests=8, device_waves=64, window_ms=40.0,
+               step_us=4.0, traj_step_us=1e-5, est_overhead_us=0.0, est_step_us=4.0,
+               est_traj_step_us=1e-5, clock=lambda: now[0])
+    big = S.submit("big", _prob(20_000), 64 * 100, 0, arrival=0.0)    # 80 ms alone
+    small = S.submit("small", _prob(1_000), 64, 1, arrival=0.0)       # 4 ms alone
+    assert abs(big.fifo_finish - 0.080004) < 1e-9
+    assert abs(small.fifo_finish - (big.fifo_finish + 0.004004)) < 1e-9
+    S.admit()
+    assert [r.tag for r in S.pick()] == ["small", "big"]
+    now[0] = 0.03   # big 30 ms late: within one window
+    assert [r.tag for r in S.pick()] == ["small", "big"]
+    now[0] = 0.05   # 50 ms late: alone, to the end of its pulse
+    assert [r.tag for r in S.pick()] == ["big"]
+    S.step()
+    assert x.launches[-1][1] == [("big", 0, 20_001)]
+    S2 = Server(FakeExec(), pool_bytes=1 << 30, max_requests=8, device_waves=64,
+                window_ms=40.0, step_us=4.0, traj_step_us=1e-5, fifo_bound=False,
+                clock=lambda: now[0])
+    S2.submit("big", _prob(20_000), 64 * 100, 0, arrival=0.0)
+    S2.submit("small", _prob(1_000), 64, 1, arrival=0.0)
+    S2.admit()
+    assert [r.tag for r in S2.pick()] == ["small", "big"]
+
+
 def test_server_rejects_bad_config():
     with pytest.raises(ValueError):
         Server(FakeExec(), 1 << 20, policy="lifo", window_ms=None)
