@@ -555,8 +555,11 @@ def served_variant(sf, n_req, loads, h_max=100.0, h_step=0.1, n_sat=200):
            "saturation_from": f"first {n_sat} requests back to back on the plain FP64 path",
            "served_policy": "srpt by estimated time left less 0.5 x waiting time, launches "
                             "filled to 8,192 wavefronts, windows of ~40 ms ending with the "
-                            "shortest request of each launch, one window in flight; a request "
-                            "alone runs its whole pulse in one launch of the plain FP64 kernel",
+                            "shortest request of each launch (requests bound by their step "
+                            "latency advance more steps), one window in flight; a request more "
+                            "than one window behind its completion on a virtual FIFO server "
+                            "runs alone to its end; a request alone runs its whole pulse in one "
+                            "launch of the plain FP64 kernel",
            "loads": []}
     for load in loads:
         rate = load * sat
