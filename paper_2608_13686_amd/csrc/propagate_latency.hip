@@ -297,16 +297,17 @@ __device__ __forceinline__ bool find_unit(const EnsPtrs& e, int n_prob, uint32_t
 }
 
 // ------------------------------------------------------------ pipelined
-// The same latency form on two wavefronts per unit of 8 trajectories, so that
-// the two halves of a step run on two SIMDs at once: wavefront 0 (the orbit
-// wavefront, lanes 2g and 2g + 1 for trajectory g) integrates (q, p, S) and
-// evaluates the four stage Hessians, two stages per lane; wavefront 1 (the
-// monodromy wavefront, 8 lanes per trajectory as above) takes the
-// prefactor, amplitude and deposit at step k and advances its columns with
-// the Hessians of step k.  The orbit wavefront runs one step ahead: in
-// iteration i it writes step i's state and Hessians into ring slot i mod 2
-// of LDS while the monodromy wavefront reads step i - 1's from the other
-// slot; one workgroup barrier per iteration hands the slots over.  The
+// The same latency form on 1 + M wavefronts per unit of 8 M trajectories
+// (M = 1 or 2), so that the two halves of a step run on different SIMDs at
+// once: wavefront 0 (the orbit wavefront, lanes 2g and 2g + 1 for trajectory
+// g) integrates (q, p, S) and evaluates the four stage Hessians, two stages
+// per lane; wavefronts 1 .. M (the monodromy wavefronts, 8 trajectories of 8
+// lanes each as above) take the prefactor, amplitude and deposit at step k
+// and advance their columns with the Hessians of step k.  The orbit
+// wavefront runs one step ahead: in iteration i it writes step i's state and
+// Hessians into ring slot i mod 2 of LDS while the monodromy wavefronts read
+// step i - 1's from the other slot; one workgroup barrier per iteration
+// hands the slots over.  A
 // monodromy wavefront spreads det R over lanes 0-2 (one cofactor term each),
 // the recombination amplitude's shells over the 8 lanes of the group, and
 // keeps each step's amplitudes in LDS, summing them across trajectories once
