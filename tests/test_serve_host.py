@@ -414,6 +414,34 @@ def test_latency_bound_request_takes_more_steps():
     assert len(small.result["windows"]) < len(big.result["windows"])
 
 
+def test_extra_steps_stay_within_a_quarter_of_the_launch():
+    """Latency-bound requests gain steps in priority order only while the
+    work they add stays under a quarter of the launch's expected duration;
+    throughput-bound requests never gain."""
+    x = FakeExec()
+    x.n_groups = 1
+    S = Server(x, pool_bytes=1 << 30, max_requests=8, window=50, device_waves=64,
+               window_ms=1.0, step_us=2.0, traj_step_us=1e-3, fifo_bound=False)
+    big = S.submit("big", _prob(9000), 64 * 200, 0)
+    smalls = [S.submit(f"s{i}", _prob(9000), 64 * 15, 1 + i) for i in range(4)]
+    S.admit()
+    picked = [smalls[0], smalls[1], smalls[2], smalls[3], big]
+    win = S.window_for(picked)
+    ents = S.entries_for(picked, win)
+    steps = {r.tag: b - a for r, a, b in ents}
+    t_step = max(2.0, (64 * 200 + 4 * 64 * 15) * 1e-3)
+    dur = win * t_step
+    w_lat = int(dur / 4.0)
+    per = 64 * 15 * 1e-3 * (w_lat - win)       # added work of one small request (us)
+    n_gain = int(0.25 * dur // per)
+    assert 0 < n_gain < 4                       # the budget binds part-way
+    assert [steps[f"s{i}"] for i in range(4)] == [w_lat] * n_gain + [win] * (4 - n_gain)
+    assert steps["big"] == win
+    # launch order: the requests with more steps first, the rest as picked
+    assert [r.tag for r, _, _ in ents] == [f"s{i}" for i in range(n_gain)] + \
+        [f"s{i}" for i in range(n_gain, 4)] + ["big"]
+
+
 def test_srpt_bounds_lateness_against_fifo():
     """A request more than one window behind its completion on a virtual FIFO
     server (one request at a time in arrival order, each at its estimated
